@@ -1,0 +1,129 @@
+/*
+ * FP64 CPU oracle for the crystallization population-balance solver.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that
+ * the GPU path is checked against.  Only the test suite, the package smoke
+ * check and the CPU-baseline leg of the benchmark may load it; the solver
+ * library never links, calls or falls back to it.  It shares no code, header,
+ * table or helper with the GPU path.
+ *
+ * What it computes (paper: "Modern, Efficient, and Differentiable Transport
+ * Equation Models using JAX", arXiv 2411.00742):
+ *   - the growth PBE, Sec. 2.1 Eq. (1), reduced to one size coordinate or
+ *     kept in two with Godunov dimensional splitting (Sec. 2.1);
+ *   - the high-resolution finite-volume flux with the van Leer limiter,
+ *     Sec. 2.1 Eq. (8) and SI S1.1 Eqs. (S1)-(S2), in the flux form
+ *     F = G (f_i + kappa/2 * psi), psi = phi(theta) * (f_{i+1} - f_i);
+ *     kappa = 1 - G dt/dL is the paper's one-step update, kappa = 1 the
+ *     method-of-lines form advanced by Shu-Osher SSP-RK3;
+ *   - the CFL time step, SI S1.1 Eq. (S3);
+ *   - the discrete solute mass balance, Sec. 2.1 Eq. (9);
+ *   - moments, SI S1.2 Eq. (S5), and the method-of-moments ODEs, Eq. (S4);
+ *   - forward-mode derivatives (dual numbers), SI S2.1-S2.2, used as the
+ *     reference gradient with the time-step schedule held fixed.
+ *
+ * Units: L um, t s, T degC, f #/(m^3 um^d), G um/s, B #/(m^3 s), C g/g.
+ * Kinetic parameter kg is in m/s and is scaled by 1e6 to um/s.
+ *
+ * Per-simulation parameter row (REF_NPAR doubles):
+ *   0 kg, 1 g, 2 kb, 3 b, 4 gamma [1/um], 5 kg2, 6 g2, 7 Eg [K], 8 Eb [K],
+ *   9 T0, 10 T1, 11 t_ramp.
+ */
+#ifndef PBE_ORACLE_H
+#define PBE_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REF_NPAR 12
+#define REF_NTAN 5          /* tangent directions: kg, g, kb, b, gamma */
+
+enum { REF_SCHEME_SSPRK3 = 0, REF_SCHEME_LW_TVD = 1 };
+enum { REF_LAW_POWER = 0, REF_LAW_ARRHENIUS = 1, REF_LAW_MLP = 2 };
+enum { REF_SOL_LINEAR = 0, REF_SOL_EXP = 1 };
+enum { REF_SIM_OK = 0, REF_SIM_NONFINITE = 1, REF_SIM_OUTFLOW = 2, REF_SIM_FALLBACK = 4 };
+
+typedef struct {
+    int32_t law, scheme, sol_law, pad_;
+    double cs0, cs1;          /* Csat = cs0 + cs1*T (linear) or cs0*exp(cs1*T) */
+    double alpha;             /* rho_c * k_v / rho_solvent, g/g per (um^3/m^3) */
+    double cfl, dt_max, t_end;
+    const float *mlp;         /* law == REF_LAW_MLP: packed closure weights (see ref_mlp_*) */
+} ref_process;
+
+/* One 1D simulation.  Inputs first, then optional outputs (NULL = skip). */
+typedef struct {
+    int32_t n;                /* cells on [0, L_max] */
+    int32_t n_samples;
+    int32_t max_steps;        /* stop after this many steps (state is then "current") */
+    int32_t n_replay;         /* >0: use dt_replay[0..n_replay) as the step sizes */
+    double L_max;
+    double C0;
+    const double *f0;         /* [n] */
+    const double *par;        /* [REF_NPAR] */
+    const double *t_samples;  /* [n_samples] ascending in (0, t_end] */
+    const double *dt_replay;
+    /* outputs */
+    double *f_samples;        /* [n_samples][n] */
+    double *mom;              /* [n_samples][4]  mu_0..mu_3 */
+    double *C;                /* [n_samples] */
+    double *f_final;          /* [n] state when the loop stops */
+    double *dt_log;           /* [max_steps] step sizes taken */
+    double *G0_log, *B_log;   /* [max_steps] rates used in each step */
+    int32_t *steps, *status;
+    double *C_final, *t_final, *outflow;
+} ref_sim1d;
+
+/* One 2D simulation, f stored [n2][n1] with L1 contiguous. */
+typedef struct {
+    int32_t n1, n2, n_samples, max_steps;
+    double L1_max, L2_max, C0;
+    const double *f0, *par, *t_samples;
+    double *mom;              /* [n_samples][4]: mu_00, mu_10, mu_01, mu_12 */
+    double *C;                /* [n_samples] */
+    double *f_final;          /* [n2][n1] */
+    double *dt_log;
+    int32_t *steps, *status;
+    double *C_final, *t_final, *outflow;
+} ref_sim2d;
+
+/* van Leer limiter phi(theta), SI Eq. (S2). */
+double ref_phi_vanleer(double theta);
+/* Limited slope psi(a, b) = phi(a/b) * b in division-safe form; 0 where a*b <= 0. */
+double ref_limited_slope(double a, double b);
+
+int ref_solve1d(const ref_process *p, ref_sim1d *s);
+/* Independent sims over a pool of n_threads std::threads (<=0: hardware concurrency).
+ * Returns the number of threads used. */
+int ref_solve1d_batch(const ref_process *p, ref_sim1d *sims, int32_t n_sims, int32_t n_threads);
+
+/* Forward-mode derivatives of the recorded samples w.r.t. (kg, g, kb, b, gamma)
+ * with the step-size schedule of the primal run held fixed.
+ * dF [n_samples][n][5], dM [n_samples][4][5], dC [n_samples][5] (each may be NULL). */
+int ref_tangent1d(const ref_process *p, ref_sim1d *s, double *dF, double *dM, double *dC);
+
+int ref_solve2d(const ref_process *p, ref_sim2d *s);
+int ref_solve2d_batch(const ref_process *p, ref_sim2d *sims, int32_t n_sims, int32_t n_threads);
+
+/* Method of moments (SI S1.2 Eq. (S4) reduced to one size coordinate, with
+ * G = G0 (1 + gamma L) and nucleation at L = 0) coupled to the solute balance,
+ * integrated with Dormand-Prince 5(4).  mu_init[4]; outputs [n_samples][4], [n_samples]. */
+int ref_mom1d(const ref_process *p, const double *par, double C0, const double *mu_init,
+              int32_t n_samples, const double *t_samples, double rtol, double atol,
+              double *mu_out, double *C_out);
+/* 2D cross moments mu_00, mu_10, mu_01, mu_11, mu_02, mu_12 (size-independent G1, G2). */
+int ref_mom2d(const ref_process *p, const double *par, double C0, const double *mu_init,
+              int32_t n_samples, const double *t_samples, double rtol, double atol,
+              double *mu_out, double *C_out);
+
+/* The worked forward-mode example of SI S2.2: y1 = sin x1/(x1+x2), y2 = (x1+x2) e^x2.
+ * out = [y1, y2, dy1/dx1, dy1/dx2, dy2/dx1, dy2/dx2]. */
+void ref_dual_example(double x1, double x2, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,355 @@
+"""Seeded synthetic inputs for the crystallization PBE solver.
+
+This module only draws inputs: random kinetics, grid sizes, operating
+conditions and seed distributions.  It holds none of the solver's arithmetic
+(no fluxes, limiters, rates, moments or mass balance), so both the HIP path and
+the FP64 CPU oracle can be fed from it without sharing any of the method.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), written out here from that
+published definition.  Uniforms take the top 53 bits; normals use Box-Muller.
+
+Units used throughout: L in micrometres, t in seconds, T in degrees Celsius,
+number density f in #/(m^3 um^d) for a d-dimensional grid, G in um/s,
+B in #/(m^3 s), concentration C in g solute per g solvent.
+
+The workload shapes follow the paper's batch cooling crystallizer (Sec. 2.1,
+Table 1: Gaussian seeds, cylinder shape factor, crystal density) with the
+sizes of the batched / 2D / gradient / closure studies this solver targets.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.special import erf
+
+MASK64 = (1 << 64) - 1
+
+# ---- integer codes shared by the C ABI, the oracle wrapper and this module --
+SCHEME_SSPRK3 = 0      # method of lines + Shu-Osher SSP-RK3, limited upwind flux
+SCHEME_LW_TVD = 1      # the paper's one-step limited Lax-Wendroff update (Eq. 8)
+LAW_POWER = 0          # G = kg*S^g (1 + gamma*L), B = kb*S^b
+LAW_ARRHENIUS = 1      # as above times exp(-E/(T+273.15)) (App. A, Eq. A.2 form)
+LAW_MLP = 2            # learned closure
+SOL_LINEAR = 0         # Csat = cs0 + cs1*T
+SOL_EXP = 1            # Csat = cs0*exp(cs1*T)   (App. A, Eq. A.1)
+
+# per-simulation parameter row (NPAR doubles)
+P_KG, P_G, P_KB, P_B, P_GAMMA, P_KG2, P_G2, P_EG, P_EB, P_T0, P_T1, P_TRAMP = range(12)
+NPAR = 12
+
+RHO_C_G_PER_UM3 = 1.11e-12          # crystal density, Table 1
+K_V = math.pi / 4.0                  # cylinder shape factor, Table 1
+RHO_SOLVENT_G_PER_M3 = 1.0e6         # 1000 kg/m^3 (not given by the paper)
+ALPHA = RHO_C_G_PER_UM3 * K_V / RHO_SOLVENT_G_PER_M3   # g/g per (um^3/m^3)
+
+CS0, CS1 = 0.1, 0.002                # linear solubility g/g and g/g/degC
+T_HOT, T_COLD, T_RAMP, T_END = 40.0, 20.0, 3600.0, 3600.0
+
+
+class SplitMix64:
+    """SplitMix64 generator (Steele, Lea, Flood 2014)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        """Uniform on [0, 1) from the top 53 bits."""
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+    def uniform_range(self, lo: float, hi: float) -> float:
+        return lo + (hi - lo) * self.uniform()
+
+    def log_uniform(self, lo: float, hi: float) -> float:
+        return math.exp(self.uniform_range(math.log(lo), math.log(hi)))
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Integer uniform on {lo, ..., hi}."""
+        return lo + min(int(self.uniform() * (hi - lo + 1)), hi - lo)
+
+    def normal(self) -> float:
+        """Standard normal by Box-Muller (one of the pair)."""
+        u1 = self.uniform()
+        u2 = self.uniform()
+        u1 = max(u1, 1e-300)
+        return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+def csat_linear(T: float) -> float:
+    """Solubility used by the workloads (an input choice, g/g)."""
+    return CS0 + CS1 * T
+
+
+def gaussian_seed_1d(n: int, L_max: float, mean: float, sd: float, total: float) -> np.ndarray:
+    """Cell averages of a Gaussian number density on n uniform cells of [0, L_max].
+
+    Cell averages come from differences of the normal CDF; the result is
+    rescaled so that sum(f)*dL equals `total` exactly (up to rounding).
+    """
+    edges = np.linspace(0.0, L_max, n + 1)
+    cdf = 0.5 * (1.0 + erf((edges - mean) / (sd * math.sqrt(2.0))))
+    dL = L_max / n
+    f = np.diff(cdf) / dL
+    f = np.maximum(f, 0.0)
+    f *= total / (f.sum() * dL)
+    return f.astype(np.float64)
+
+
+def gaussian_seed_2d(n1: int, n2: int, L1_max: float, L2_max: float,
+                     mean: tuple, sd: tuple, rho: float, total: float) -> np.ndarray:
+    """Bivariate normal density sampled at cell centres, shape [n2][n1] (L1 fastest).
+
+    Rescaled so that sum(f)*dL1*dL2 equals `total`.
+    """
+    d1, d2 = L1_max / n1, L2_max / n2
+    x = (np.arange(n1) + 0.5) * d1
+    y = (np.arange(n2) + 0.5) * d2
+    z1 = (x[None, :] - mean[0]) / sd[0]
+    z2 = (y[:, None] - mean[1]) / sd[1]
+    q = (z1 * z1 - 2.0 * rho * z1 * z2 + z2 * z2) / (1.0 - rho * rho)
+    f = np.exp(-0.5 * q)
+    f *= total / (f.sum() * d1 * d2)
+    return np.ascontiguousarray(f, dtype=np.float64)
+
+
+@dataclass
+class Problem:
+    """A batch of independent simulations plus the process settings they share.
+
+    ndim == 1: n_cells[S], L_max[S], f0 packed [sum N_s].
+    ndim == 2: n_cells[S, 2] = (n1, n2), L_max[S, 2], f0 packed [sum n1*n2],
+               each sim stored [n2][n1] with L1 contiguous.
+    par[S, NPAR]: kinetics and operating conditions (see the P_* indices).
+    """
+    ndim: int
+    n_cells: np.ndarray
+    L_max: np.ndarray
+    f0: np.ndarray
+    C0: np.ndarray
+    par: np.ndarray
+    t_samples: np.ndarray
+    law: int = LAW_POWER
+    scheme: int = SCHEME_SSPRK3
+    sol_law: int = SOL_LINEAR
+    cs0: float = CS0
+    cs1: float = CS1
+    alpha: float = ALPHA
+    cfl: float = 0.5
+    dt_max: float = 1.0
+    t_end: float = T_END
+    name: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_sims(self) -> int:
+        return int(self.C0.shape[0])
+
+    def cells_per_sim(self) -> np.ndarray:
+        if self.ndim == 1:
+            return self.n_cells.astype(np.int64)
+        return (self.n_cells[:, 0].astype(np.int64) * self.n_cells[:, 1].astype(np.int64))
+
+    def offsets(self) -> np.ndarray:
+        c = self.cells_per_sim()
+        off = np.zeros(c.shape[0] + 1, dtype=np.int64)
+        np.cumsum(c, out=off[1:])
+        return off
+
+    def f0_of(self, s: int) -> np.ndarray:
+        off = self.offsets()
+        f = self.f0[off[s]:off[s + 1]]
+        if self.ndim == 2:
+            n1, n2 = int(self.n_cells[s, 0]), int(self.n_cells[s, 1])
+            return f.reshape(n2, n1)
+        return f
+
+    def subset(self, idx) -> "Problem":
+        """The same problem restricted to the simulations in `idx` (in that order)."""
+        idx = np.asarray(idx, dtype=np.int64)
+        off = self.offsets()
+        f0 = np.concatenate([self.f0[off[s]:off[s + 1]] for s in idx]) if len(idx) else np.zeros(0)
+        return Problem(ndim=self.ndim, n_cells=self.n_cells[idx].copy(), L_max=self.L_max[idx].copy(),
+                       f0=f0, C0=self.C0[idx].copy(), par=self.par[idx].copy(),
+                       t_samples=self.t_samples.copy(), law=self.law, scheme=self.scheme,
+                       sol_law=self.sol_law, cs0=self.cs0, cs1=self.cs1, alpha=self.alpha,
+                       cfl=self.cfl, dt_max=self.dt_max, t_end=self.t_end,
+                       name=self.name + "[subset]", extra=dict(self.extra))
+
+    def with_(self, **kw) -> "Problem":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Problem(**d)
+
+
+def _par_row(kg, g, kb, b, gamma=0.0, kg2=0.0, g2=0.0, Eg=0.0, Eb=0.0,
+             T0=T_HOT, T1=T_COLD, t_ramp=T_RAMP) -> np.ndarray:
+    r = np.zeros(NPAR)
+    r[P_KG], r[P_G], r[P_KB], r[P_B], r[P_GAMMA] = kg, g, kb, b, gamma
+    r[P_KG2], r[P_G2], r[P_EG], r[P_EB] = kg2, g2, Eg, Eb
+    r[P_T0], r[P_T1], r[P_TRAMP] = T0, T1, t_ramp
+    return r
+
+
+def draw_kinetics(rng: SplitMix64, with_gamma: bool):
+    """Draw (kg, g, kb, b, gamma) in the ranges of the single-simulation workload."""
+    kg = rng.log_uniform(1e-7, 1e-6)
+    g = rng.uniform_range(1.0, 2.0)
+    kb = rng.log_uniform(1e8, 1e10)
+    b = rng.uniform_range(1.0, 3.0)
+    gamma = rng.uniform_range(0.0, 2e-3) if with_gamma else 0.0
+    return kg, g, kb, b, gamma
+
+
+def uniform_samples(n: int, t_end: float = T_END) -> np.ndarray:
+    return np.array([t_end * (k + 1) / n for k in range(n)], dtype=np.float64)
+
+
+SEED_BASE = 241100742
+
+
+def single_sim(variant: str = "drawn", n: int = 200, t_end: float = T_END,
+               n_samples: int = 20) -> Problem:
+    """One 1D simulation: 200 cells on [0, 1000] um, Gaussian seed 200 +- 30 um, 1e9 #/m^3.
+
+    variant "drawn": kinetics drawn from the seeded generator;
+    variant "mid":   kg = 3e-7 m/s, g = 1.5, kb = 1e9 #/m^3/s, b = 2.
+    """
+    rng = SplitMix64(SEED_BASE + 0)
+    if variant == "mid":
+        kg, g, kb, b, gamma = 3e-7, 1.5, 1e9, 2.0, 0.0
+    else:
+        kg, g, kb, b, gamma = draw_kinetics(rng, with_gamma=False)
+    L_max = 1000.0
+    f0 = gaussian_seed_1d(n, L_max, 200.0, 30.0, 1e9)
+    return Problem(ndim=1, n_cells=np.array([n], dtype=np.int32), L_max=np.array([L_max]),
+                   f0=f0, C0=np.array([csat_linear(T_HOT)]),
+                   par=_par_row(kg, g, kb, b, gamma, t_ramp=T_RAMP)[None, :],
+                   t_samples=uniform_samples(n_samples, t_end), t_end=t_end,
+                   name=f"single-{variant}-N{n}")
+
+
+def batched(n_sims: int = 4096, n_lo: int = 200, n_hi: int = 2000, t_end: float = T_END,
+            n_samples: int = 20, seed_offset: int = 1) -> Problem:
+    """Many independent 1D simulations with uneven grids and per-sim kinetics.
+
+    N ~ U{n_lo..n_hi} on [0, 1000] um; kinetics as the single simulation plus
+    size-dependent growth gamma ~ U[0, 2e-3] 1/um; Gaussian seed 200 +- 30 um.
+    """
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    ns, pars, seeds = [], [], []
+    for _ in range(n_sims):
+        kg, g, kb, b, gamma = draw_kinetics(rng, with_gamma=True)
+        n = rng.randint(n_lo, n_hi)
+        ns.append(n)
+        pars.append(_par_row(kg, g, kb, b, gamma))
+        seeds.append(gaussian_seed_1d(n, 1000.0, 200.0, 30.0, 1e9))
+    return Problem(ndim=1, n_cells=np.array(ns, dtype=np.int32), L_max=np.full(n_sims, 1000.0),
+                   f0=np.concatenate(seeds), C0=np.full(n_sims, csat_linear(T_HOT)),
+                   par=np.array(pars), t_samples=uniform_samples(n_samples, t_end), t_end=t_end,
+                   name=f"batched-{n_sims}x[{n_lo},{n_hi}]")
+
+
+def shape_2d(n_sims: int = 64, n_lo: int = 256, n_hi: int = 1024, t_end: float = T_END,
+             n_samples: int = 20, seed_offset: int = 2, square: bool = True) -> Problem:
+    """2D length x width simulations on [0,1200] x [0,600] um (Table 1 domain and seed).
+
+    n ~ U{n_lo..n_hi}; grids n x n (or independent n1, n2 when square=False);
+    bivariate Gaussian seed (400, 250) +- (30, 30) um, correlation ~ U[0, 0.5],
+    total 1e9 #/m^3; per-axis (kg_m, g_m) and (kb, b) from the 1D ranges.
+    """
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    ncs, pars, seeds = [], [], []
+    for _ in range(n_sims):
+        kg1 = rng.log_uniform(1e-7, 1e-6)
+        g1 = rng.uniform_range(1.0, 2.0)
+        kg2 = rng.log_uniform(1e-7, 1e-6)
+        g2 = rng.uniform_range(1.0, 2.0)
+        kb = rng.log_uniform(1e8, 1e10)
+        b = rng.uniform_range(1.0, 3.0)
+        rho = rng.uniform_range(0.0, 0.5)
+        n1 = rng.randint(n_lo, n_hi)
+        n2 = n1 if square else rng.randint(n_lo, n_hi)
+        ncs.append((n1, n2))
+        pars.append(_par_row(kg1, g1, kb, b, 0.0, kg2, g2))
+        seeds.append(gaussian_seed_2d(n1, n2, 1200.0, 600.0, (400.0, 250.0), (30.0, 30.0), rho, 1e9).ravel())
+    return Problem(ndim=2, n_cells=np.array(ncs, dtype=np.int32), L_max=np.tile([1200.0, 600.0], (n_sims, 1)),
+                   f0=np.concatenate(seeds), C0=np.full(n_sims, csat_linear(T_HOT)), par=np.array(pars),
+                   t_samples=uniform_samples(n_samples, t_end), t_end=t_end,
+                   name=f"shape2d-{n_sims}x[{n_lo},{n_hi}]^2")
+
+
+def estimation(n_sims: int = 1024, n: int = 1000, t_end: float = T_END, n_samples: int = 20,
+               seed_offset: int = 3, spread: float = 0.3):
+    """Parameter-estimation workload: truth kinetics and perturbed starting guesses.
+
+    Returns (problem_at_guess, truth_par, noise) where noise[S, n_samples, 5]
+    are standard normals for 2% multiplicative measurement noise on the four
+    moments and C, and the guesses are truth * exp(spread*u), u ~ U[-1, 1].
+    """
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    truth, guess = [], []
+    for _ in range(n_sims):
+        kg, g, kb, b, _ = draw_kinetics(rng, with_gamma=False)
+        truth.append(_par_row(kg, g, kb, b))
+        u = [rng.uniform_range(-1.0, 1.0) for _ in range(4)]
+        guess.append(_par_row(kg * math.exp(spread * u[0]), g * math.exp(spread * u[1]),
+                              kb * math.exp(spread * u[2]), b * math.exp(spread * u[3])))
+    noise = np.array([[[rng.normal() for _ in range(5)] for _ in range(n_samples)] for _ in range(n_sims)])
+    f0 = gaussian_seed_1d(n, 1000.0, 200.0, 30.0, 1e9)
+    prob = Problem(ndim=1, n_cells=np.full(n_sims, n, dtype=np.int32), L_max=np.full(n_sims, 1000.0),
+                   f0=np.tile(f0, n_sims), C0=np.full(n_sims, csat_linear(T_HOT)), par=np.array(guess),
+                   t_samples=uniform_samples(n_samples, t_end), t_end=t_end,
+                   name=f"estimation-{n_sims}xN{n}")
+    return prob, np.array(truth), noise
+
+
+def closure(n_sims: int = 4096, n: int = 500, t_end: float = T_END, n_samples: int = 20,
+            seed_offset: int = 4):
+    """Learned-closure workload: one shared ground-truth law, varied operating conditions.
+
+    Ground truth: power law times an Arrhenius temperature factor (the form of
+    App. A, Eq. A.2), which the plain four-parameter power law cannot express.
+    Per sim: C0 = Csat(40)*(1 + U[0, 0.1]), final temperature T1 ~ U[15, 25],
+    seed mean ~ U[150, 250] um.  Returns (problem_with_truth_law, split) where
+    split[s] is True for training sims (80%) and False for held-out ones.
+    """
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    Eg, Eb = 4000.0, 6000.0
+    Tref = 30.0 + 273.15
+    kg = 4e-7 * math.exp(Eg / Tref)
+    kb = 2e9 * math.exp(Eb / Tref)
+    pars, seeds, C0, split = [], [], [], []
+    for _ in range(n_sims):
+        c_rel = rng.uniform_range(0.0, 0.1)
+        T1 = rng.uniform_range(15.0, 25.0)
+        mean = rng.uniform_range(150.0, 250.0)
+        split.append(rng.uniform() < 0.8)
+        pars.append(_par_row(kg, 1.5, kb, 2.0, 0.0, Eg=Eg, Eb=Eb, T1=T1))
+        seeds.append(gaussian_seed_1d(n, 1000.0, mean, 30.0, 1e9))
+        C0.append(csat_linear(T_HOT) * (1.0 + c_rel))
+    prob = Problem(ndim=1, n_cells=np.full(n_sims, n, dtype=np.int32), L_max=np.full(n_sims, 1000.0),
+                   f0=np.concatenate(seeds), C0=np.array(C0), par=np.array(pars),
+                   t_samples=uniform_samples(n_samples, t_end), t_end=t_end, law=LAW_ARRHENIUS,
+                   name=f"closure-{n_sims}xN{n}")
+    return prob, np.array(split)
+
+
+def random_tiny(seed: int, n: int, t_end: float = 50.0, n_samples: int = 5, gamma: bool = True) -> Problem:
+    """A small randomized single simulation for brute-force style checks."""
+    rng = SplitMix64(SEED_BASE + 1000 + seed)
+    kg, g, kb, b, gm = draw_kinetics(rng, with_gamma=gamma)
+    mean = rng.uniform_range(0.3, 0.6) * 1000.0
+    f0 = gaussian_seed_1d(n, 1000.0, mean, 60.0, 1e9)
+    C0 = csat_linear(T_HOT) * (1.0 + rng.uniform_range(0.02, 0.1))
+    return Problem(ndim=1, n_cells=np.array([n], dtype=np.int32), L_max=np.array([1000.0]), f0=f0,
+                   C0=np.array([C0]), par=_par_row(kg, g, kb, b, gm)[None, :],
+                   t_samples=uniform_samples(n_samples, t_end), t_end=t_end, name=f"tiny-{seed}-N{n}")
