@@ -1,0 +1,155 @@
+/*
+ * pbe.h - C ABI of the MI355X (gfx950) crystallization population-balance solver.
+ *
+ * The library advances many independent batch-crystallizer simulations on one
+ * GPU.  Each simulation solves the growth population balance (paper Sec. 2.1,
+ * Eq. (1), in one size coordinate or in two with Godunov splitting) with the
+ * high-resolution finite-volume flux and van Leer limiter (Eq. (8), SI
+ * Eqs. (S1)-(S2)), a CFL-limited step (SI Eq. (S3)), nucleation entering as a
+ * flux at L = 0, and the discrete solute balance (Eq. (9)) that sets the
+ * supersaturation driving the rate laws (App. A).  pbe_grad returns exact
+ * derivatives of recorded outputs (the paper's reverse-mode use, Sec. 4.1,
+ * Eq. (10)) through a hand-written discrete adjoint with checkpointing.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a pbe_status code; nothing throws across the ABI.
+ *     Argument errors are detected on the host before any device work.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Units: L um, t s, T degC, f #/(m^3 um^ndim), G um/s, B #/(m^3 s),
+ *     C g solute / g solvent.  The rate constant kg is given in m/s.
+ *   - Layouts: 1D sims are packed back to back, sim s occupying
+ *     [off_s, off_s + N_s) with off_0 = 0, off_{s+1} = off_s + N_s.
+ *     2D sims occupy n1_s*n2_s cells stored [n2][n1] (L1 contiguous).
+ *   - Per-sim parameter row par[s*PBE_NPAR + k], k = PBE_P_*.
+ */
+#ifndef PBE_H
+#define PBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbe_handle pbe_handle;
+
+typedef enum {
+    PBE_OK = 0,
+    PBE_EINVAL = -1,        /* invalid argument (checked on the host, nothing launched) */
+    PBE_ENOMEM = -2,        /* device allocation failed; nothing leaked */
+    PBE_EDEVICE = -3,       /* HIP runtime error */
+    PBE_ENONFINITE = -4,    /* reserved: per-sim non-finite states are reported in status_out */
+    PBE_ESTATE = -5,        /* call not valid in the handle's current state */
+    PBE_EUNSUPPORTED = -6   /* combination of options not implemented */
+} pbe_status;
+
+enum { PBE_SCHEME_SSPRK3 = 0,   /* method of lines, Shu-Osher SSP-RK3, kappa = 1 flux */
+       PBE_SCHEME_LW_TVD = 1 }; /* the paper's one-step limited update, Eq. (8) */
+enum { PBE_LAW_POWER = 0,       /* G = kg S^g (1 + gamma L), B = kb S^b, S = C/Csat - 1 */
+       PBE_LAW_ARRHENIUS = 1,   /* power law times exp(-Eg/(T+273.15)), exp(-Eb/(T+273.15)) (App. A, Eq. A.2) */
+       PBE_LAW_MLP = 2 };       /* learned closure for (G0, B); see pbe_problem.mlp */
+enum { PBE_SOL_LINEAR = 0,      /* Csat = cs0 + cs1 T */
+       PBE_SOL_EXP = 1 };       /* Csat = cs0 exp(cs1 T) (App. A, Eq. A.1) */
+/* per-sim status bits written to status_out */
+enum { PBE_SIM_OK = 0, PBE_SIM_NONFINITE = 1, PBE_SIM_OUTFLOW = 2, PBE_SIM_FALLBACK = 4 };
+/* pbe_problem.flags */
+enum { PBE_FLAG_DEVICE_PTRS = 1,  /* output/cotangent pointers are device memory, stream-ordered */
+       PBE_FLAG_RECORD_F = 2 };   /* record the number density at every sample time */
+
+/* per-sim parameter row */
+enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G2, PBE_P_EG, PBE_P_EB,
+       PBE_P_T0, PBE_P_T1, PBE_P_TRAMP, PBE_NPAR };
+#define PBE_NGRAD 5   /* pbe_grad returns d/d(kg, g, kb, b, gamma) per sim */
+
+typedef struct {
+    int32_t ndim;               /* 1 or 2 */
+    int32_t n_sims;             /* S >= 1 */
+    const int32_t *n_cells;     /* host [S*ndim]; 1D: N_s in [4, 2048]; 2D: (n1_s, n2_s) in [4, 4096] */
+    const double *L_max;        /* host [S*ndim] domain lengths, um */
+    const double *f0;           /* host, packed initial densities (see layouts) */
+    const double *C0;           /* host [S] initial concentration */
+    const double *par;          /* host [S*PBE_NPAR] kinetics and the cooling ramp
+                                   T(t) = T0 + (T1 - T0) min(t, t_ramp)/t_ramp */
+    const float *mlp;           /* host, law == PBE_LAW_MLP only: closure weights (pbe_mlp_nparams floats) */
+    int32_t law, scheme, sol_law;
+    int32_t n_samples;          /* >= 1 */
+    double cs0, cs1;            /* solubility coefficients */
+    double alpha;               /* rho_c k_v / rho_solvent: C drop per unit volume moment */
+    double cfl;                 /* Courant number nu in (0, 1] */
+    double dt_max;              /* cap on the step size, s */
+    double t_end;               /* end time, s */
+    const double *t_samples;    /* host [n_samples], strictly ascending in (0, t_end] */
+    int32_t ckpt_every;         /* 0: no gradients; K > 0: checkpoint every K steps for pbe_grad (1D) */
+    int32_t max_steps;          /* per-sim step budget (0: derived from t_end, dt_max and the CFL bound) */
+    int32_t flags;              /* PBE_FLAG_* */
+    int32_t reserved;
+} pbe_problem;
+
+/* Create a handle: validates `p`, deep-copies every input to device memory
+ * (the caller may free its buffers on return), orders the sims for the
+ * persistent launch and records the launch graph.  `hip_stream` is the HIP
+ * stream all work is ordered on (NULL = default stream).
+ * Errors: PBE_EINVAL (any field out of range), PBE_ENOMEM, PBE_EDEVICE. */
+int pbe_create(const pbe_problem *p, void *hip_stream, pbe_handle **out);
+
+/* Advance every unfinished simulation by at most n_steps time steps from its
+ * current state (the initial condition after create/reset).  Samples falling
+ * inside are recorded.  If n_active_out != NULL the call waits and stores the
+ * number of sims that have not reached t_end. */
+int pbe_step(pbe_handle *h, int32_t n_steps, int32_t *n_active_out);
+
+/* Restart from the initial condition. */
+int pbe_reset(pbe_handle *h);
+
+/* Solve every simulation from the initial condition to t_end (one graph launch)
+ * and write:
+ *   f_out      RECORD_F: densities at each sample, sim-major [s][sample][cells_s];
+ *              otherwise the final densities, packed [sum cells].
+ *   mom_out    [S][n_samples][4]: 1D mu_0..mu_3 (SI Eq. (S5), midpoint rule);
+ *              2D mu_00, mu_10, mu_01, mu_12.
+ *   C_out      [S][n_samples] concentration at the samples.
+ *   steps_out  [S] steps taken;  status_out [S] PBE_SIM_* bits.
+ * Any output may be NULL.  With PBE_FLAG_DEVICE_PTRS outputs are device
+ * pointers written stream-ordered and the call returns without waiting;
+ * otherwise they are host pointers and the call blocks.
+ * With ckpt_every > 0 the forward pass also stores checkpoints for pbe_grad. */
+int pbe_solve(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
+              int32_t *steps_out, int32_t *status_out);
+
+/* Copy the current state (after pbe_step) and the samples recorded so far
+ * into the same outputs as pbe_solve (f_out is the current density unless
+ * RECORD_F).  Samples not yet reached read as 0. */
+int pbe_fetch(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
+              int32_t *steps_out, int32_t *status_out);
+
+/* Vector-Jacobian product of the outputs of the last pbe_solve (1D only):
+ * given cotangents gf (shape of f_out), gmom (shape of mom_out), gC (shape
+ * of C_out) - each may be NULL for zero - write
+ *   gpar_out  [S][PBE_NGRAD] = d<cot, outputs>/d(kg, g, kb, b, gamma) per sim,
+ *   gmlp_out  law == MLP: d/d(closure weights) summed over sims (fp32), else unused.
+ * The step-size schedule of the forward solve is held fixed (it is not
+ * differentiated).  Requires ckpt_every > 0 and a completed pbe_solve
+ * (PBE_ESTATE otherwise). */
+int pbe_grad(pbe_handle *h, const double *gf, const double *gmom, const double *gC,
+             double *gpar_out, float *gmlp_out);
+
+/* Replace every sim's parameter row (host pointer [S*PBE_NPAR], same checks
+ * as pbe_create) without rebuilding the handle, e.g. between optimizer
+ * iterations; the handle restarts from the initial condition.  Waits for the
+ * handle's queued work first. */
+int pbe_set_par(pbe_handle *h, const double *par);
+
+/* Release all device memory of the handle.  NULL is a no-op. */
+void pbe_destroy(pbe_handle *h);
+
+/* Static message for a pbe_status code. */
+const char *pbe_strerror(int code);
+
+/* Elapsed device time (ms) of the last pbe_solve / pbe_grad kernel work,
+ * measured with HIP events on the handle's stream around the launch. */
+int pbe_last_kernel_ms(pbe_handle *h, float *solve_ms, float *grad_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBE_H */

@@ -1,0 +1,195 @@
+"""MI355X (gfx950) crystallization population-balance solver.
+
+Thin ctypes binding of the C ABI in include/pbe.h (libpbe.so, built in-tree
+by paper_2411_00742_amd/build.py).  The binding only marshals arguments:
+torch supplies device memory for the outputs and the HIP stream; every step of
+the solve runs in the library's HIP kernels.  There is no CPU fallback: if the
+library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import workloads  # noqa: F401  (seeded input generators)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbe.so")
+
+PBE_OK, PBE_EINVAL, PBE_ENOMEM, PBE_EDEVICE, PBE_ENONFINITE, PBE_ESTATE, PBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FLAG_DEVICE_PTRS, FLAG_RECORD_F = 1, 2
+SIM_OK, SIM_NONFINITE, SIM_OUTFLOW, SIM_FALLBACK, SIM_STEPCAP = 0, 1, 2, 4, 8
+NPAR = 12
+NGRAD = 5
+
+# every entry point of include/pbe.h
+EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
+           "pbe_destroy", "pbe_strerror", "pbe_last_kernel_ms"]
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class PbeProblem(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n_sims", C.c_int32),
+                ("n_cells", _ip), ("L_max", _dp), ("f0", _dp), ("C0", _dp), ("par", _dp),
+                ("mlp", C.POINTER(C.c_float)),
+                ("law", C.c_int32), ("scheme", C.c_int32), ("sol_law", C.c_int32), ("n_samples", C.c_int32),
+                ("cs0", C.c_double), ("cs1", C.c_double), ("alpha", C.c_double), ("cfl", C.c_double),
+                ("dt_max", C.c_double), ("t_end", C.c_double), ("t_samples", _dp),
+                ("ckpt_every", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class PBEError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = lib().pbe_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpbe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2411_00742_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.pbe_create.argtypes = [C.POINTER(PbeProblem), vp, C.POINTER(vp)]
+        L.pbe_step.argtypes = [vp, C.c_int32, _ip]
+        L.pbe_reset.argtypes = [vp]
+        L.pbe_solve.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pbe_fetch.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pbe_grad.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pbe_set_par.argtypes = [vp, _dp]
+        L.pbe_destroy.argtypes = [vp]
+        L.pbe_destroy.restype = None
+        L.pbe_strerror.argtypes = [C.c_int]
+        L.pbe_strerror.restype = C.c_char_p
+        L.pbe_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        for name in EXPORTS:
+            if name not in ("pbe_destroy", "pbe_strerror"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != PBE_OK:
+        raise PBEError(rc, what)
+
+
+def _arr(x, dtype):
+    return np.ascontiguousarray(x, dtype=dtype)
+
+
+def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, max_steps=0):
+    """Build the pbe_problem struct for a workloads.Problem; returns (struct, keepalive)."""
+    keep = dict(n_cells=_arr(prob.n_cells.reshape(-1), np.int32), L_max=_arr(prob.L_max.reshape(-1), np.float64),
+                f0=_arr(prob.f0, np.float64), C0=_arr(prob.C0, np.float64), par=_arr(prob.par, np.float64),
+                t_samples=_arr(prob.t_samples, np.float64))
+    flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0)
+    st = PbeProblem(ndim=prob.ndim, n_sims=prob.n_sims,
+                    n_cells=keep["n_cells"].ctypes.data_as(_ip), L_max=keep["L_max"].ctypes.data_as(_dp),
+                    f0=keep["f0"].ctypes.data_as(_dp), C0=keep["C0"].ctypes.data_as(_dp),
+                    par=keep["par"].ctypes.data_as(_dp), mlp=None,
+                    law=prob.law, scheme=prob.scheme, sol_law=prob.sol_law, n_samples=len(prob.t_samples),
+                    cs0=prob.cs0, cs1=prob.cs1, alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max,
+                    t_end=prob.t_end, t_samples=keep["t_samples"].ctypes.data_as(_dp),
+                    ckpt_every=ckpt_every, max_steps=max_steps, flags=flags, reserved=0)
+    return st, keep
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One pbe_handle: a batch of simulations resident on the GPU.
+
+    Outputs are torch tensors on the current CUDA (HIP) device; all work is
+    ordered on torch's current stream.
+    """
+
+    def __init__(self, prob, ckpt_every: int = 0, record_f: bool = False, max_steps: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_2411_00742_amd needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.prob = prob
+        self.record_f = record_f
+        self.ckpt_every = ckpt_every
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        st, keep = make_problem_struct(prob, ckpt_every, record_f, True, max_steps)
+        self._h = C.c_void_p()
+        _check(lib().pbe_create(C.byref(st), C.c_void_p(self.stream.cuda_stream), C.byref(self._h)), "pbe_create")
+        del keep
+        self.S = prob.n_sims
+        self.ns = len(prob.t_samples)
+        self.total = int(prob.cells_per_sim().sum())
+
+    # --- output buffers -------------------------------------------------------
+    def _outputs(self):
+        t = self.torch
+        nf = self.total * self.ns if self.record_f else self.total
+        kw = dict(device=self.device)
+        return dict(f=t.empty(nf, dtype=t.float64, **kw), mom=t.empty((self.S, self.ns, 4), dtype=t.float64, **kw),
+                    C=t.empty((self.S, self.ns), dtype=t.float64, **kw), steps=t.empty(self.S, dtype=t.int32, **kw),
+                    status=t.empty(self.S, dtype=t.int32, **kw))
+
+    def solve(self, out=None):
+        """Solve every simulation from the initial condition; returns dict of device tensors."""
+        o = out if out is not None else self._outputs()
+        _check(lib().pbe_solve(self._h, _ptr(o["f"]), _ptr(o["mom"]), _ptr(o["C"]), _ptr(o["steps"]),
+                               _ptr(o["status"])), "pbe_solve")
+        return o
+
+    def step(self, n_steps: int) -> int:
+        n_active = C.c_int32()
+        _check(lib().pbe_step(self._h, n_steps, C.byref(n_active)), "pbe_step")
+        return n_active.value
+
+    def fetch(self):
+        o = self._outputs()
+        _check(lib().pbe_fetch(self._h, _ptr(o["f"]), _ptr(o["mom"]), _ptr(o["C"]), _ptr(o["steps"]),
+                               _ptr(o["status"])), "pbe_fetch")
+        return o
+
+    def reset(self):
+        _check(lib().pbe_reset(self._h), "pbe_reset")
+
+    def set_par(self, par):
+        p = _arr(par, np.float64)
+        assert p.shape == (self.S, NPAR)
+        _check(lib().pbe_set_par(self._h, p.ctypes.data_as(_dp)), "pbe_set_par")
+
+    def grad(self, gf=None, gmom=None, gC=None):
+        """d<cotangents, outputs>/d(kg, g, kb, b, gamma) per sim, as a [S, 5] device tensor."""
+        t = self.torch
+        g = t.empty((self.S, NGRAD), dtype=t.float64, device=self.device)
+        cot = [None if x is None else x.to(device=self.device, dtype=t.float64).contiguous() for x in (gf, gmom, gC)]
+        _check(lib().pbe_grad(self._h, _ptr(cot[0]), _ptr(cot[1]), _ptr(cot[2]), _ptr(g), None), "pbe_grad")
+        return g
+
+    def last_kernel_ms(self):
+        a, b = C.c_float(), C.c_float()
+        _check(lib().pbe_last_kernel_ms(self._h, C.byref(a), C.byref(b)), "pbe_last_kernel_ms")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pbe_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,252 @@
+// Device-side building blocks of the 1D finite-volume step (gfx950).
+//
+// Mapping: one wavefront owns one simulation for its whole time loop.  The
+// N cells are held in registers, K = ceil(N/64) consecutive cells per lane,
+// right-aligned: lane l, slot k holds cell i = l*K + k - pad with
+// pad = 64*K - N.  Right alignment puts the last cell (and so the outflow face
+// at L_max) at lane 63, slot K-1 for every N; the pad slots on the left hold
+// the inflow ghost value, which makes the face at L = 0 carry exactly the
+// nucleation flux.  Neighbour cells across lanes move with DPP wave shifts;
+// nothing touches LDS or HBM inside the time loop.
+//
+// Numerics follow the paper (arXiv 2411.00742): flux-limited upwind fluxes
+// with the van Leer limiter (Sec. 2.1 Eq. (8), SI Eqs. (S1)-(S2)), CFL step
+// (SI Eq. (S3)), discrete solute balance (Eq. (9)), rates driven by the
+// supersaturation (App. A).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dmath.h"
+#include "pbe.h"
+
+namespace pbe {
+namespace dev {
+
+// ---------------------------------------------------------------- wave helpers
+// lane l receives v from lane l-1; lane 0 receives `fill` (DPP wave_shr:1)
+__device__ __forceinline__ double shift_from_left(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// lane l receives v from lane l+1; lane 63 receives `fill` (DPP wave_shl:1)
+__device__ __forceinline__ double shift_from_right(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    // rows outside ROW_MASK (and invalid source lanes) read 0
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+// Wave-uniform copy of a value every lane already agrees on (first active
+// lane, into scalar registers).  Used on the per-step scalars (t, C, rates,
+// dt) so the compiler keeps the time loop's control flow scalar.
+__device__ __forceinline__ double uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Sum over the 64 lanes with DPP (pairs, quads, half rows, rows, then the
+// row broadcasts); the total lands in lane 63 and is read back as a
+// wave-uniform scalar, so everything computed from it stays scalar.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_move<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);   // row_mirror
+    v += dpp_move<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return lane_value(v, 63);
+}
+
+// ---------------------------------------------------------------- process
+struct Process {
+    int law, scheme, sol_law;
+    double cs0, cs1, alpha, cfl, dt_max, t_end;
+};
+
+struct SimParams {
+    double kg, g, kb, b, gamma, Eg, Eb, T0, T1, tr;
+};
+
+__device__ __forceinline__ SimParams load_params(const double* P) {
+    SimParams q;
+    q.kg = P[PBE_P_KG]; q.g = P[PBE_P_G]; q.kb = P[PBE_P_KB]; q.b = P[PBE_P_B]; q.gamma = P[PBE_P_GAMMA];
+    q.Eg = P[PBE_P_EG]; q.Eb = P[PBE_P_EB]; q.T0 = P[PBE_P_T0]; q.T1 = P[PBE_P_T1]; q.tr = P[PBE_P_TRAMP];
+    return q;
+}
+
+// cooling ramp T0 -> T1 over tr seconds, then held
+__device__ __forceinline__ double temperature(const SimParams& q, double t) {
+    const double frac = q.tr > 0.0 ? fmin(t, q.tr) / q.tr : 1.0;
+    return q.T0 + (q.T1 - q.T0) * frac;
+}
+__device__ __forceinline__ double solubility(const Process& p, double T) {
+    return p.sol_law == PBE_SOL_EXP ? p.cs0 * exp64(p.cs1 * T) : p.cs0 + p.cs1 * T;
+}
+
+// Rates at the current concentration.  S = C/Csat - 1; growth G0 (um/s, at
+// L = 0) and nucleation B act only for S > 0.  S^g and S^b share one log.
+struct Rates {
+    double G0, B, S, lnS, arrG, arrB;   // lnS and the Arrhenius factors are kept for the adjoint
+};
+__device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& q, double C, double t) {
+    Rates r;
+    const double T = temperature(q, t);
+    r.S = C / solubility(p, T) - 1.0;
+    r.G0 = 0.0; r.B = 0.0; r.lnS = 0.0; r.arrG = 1.0; r.arrB = 1.0;
+    if (r.S > 0.0) {
+        r.lnS = log64(r.S);
+        if (p.law == PBE_LAW_ARRHENIUS) {
+            r.arrG = exp64(-q.Eg / (T + 273.15));
+            r.arrB = exp64(-q.Eb / (T + 273.15));
+        }
+        r.G0 = 1e6 * q.kg * exp64(q.g * r.lnS) * r.arrG;
+        r.B = q.kb * exp64(q.b * r.lnS) * r.arrB;
+    }
+    r.G0 = uniform(r.G0);
+    r.B = uniform(r.B);
+    r.S = uniform(r.S);
+    return r;
+}
+
+// Step size: CFL limit nu*dL/max_face G (G grows with L, so the max is at
+// L_max), capped by dt_max, landing exactly on the next sample time.
+__device__ __forceinline__ bool choose_dt(const Process& p, double G0, double gamma, double Lmax, double dL, double t,
+                                          double t_next, double* dt) {
+    const double Gmax = G0 * (1.0 + gamma * Lmax);
+    const double lim = Gmax > 0.0 ? p.cfl * dL / Gmax : __builtin_huge_val();
+    const double d = fmin(lim, p.dt_max);
+    const double rem = t_next - t;
+    const bool hit = d >= rem - 1e-12 * p.t_end;
+    *dt = uniform(hit ? rem : d);
+    return uniform((int)hit) != 0;
+}
+
+// ---------------------------------------------------------------- flux
+// van Leer limited slope psi = phi(a/b)*b = 2ab/(a+b) when a and b share a
+// strict sign, else 0 (SI Eqs. (S1)-(S2) in division-safe form).
+__device__ __forceinline__ double limited_slope(double a, double b) {
+    const double p = a * b;
+    const bool same = p > 0.0;
+    // branch-free: divide 0 by 1 where the slopes disagree
+    return (same ? p + p : 0.0) / (same ? a + b : 1.0);
+}
+
+// Face value H = w (f_i + kappa/2 psi) with w = G(L_face)/G0; the face flux is
+// G0*H.  kappa = 1 (method of lines) or 1 - nu_face (one-step update, Eq. (8)).
+template <int SCHEME>
+__device__ __forceinline__ double face_value(double um1, double ui, double up1, double w, double c) {
+    const double psi = limited_slope(ui - um1, up1 - ui);
+    if (SCHEME == PBE_SCHEME_LW_TVD) {
+        const double kappa = 1.0 - c * w;
+        return w * (ui + 0.5 * kappa * psi);
+    }
+    return w * (ui + 0.5 * psi);
+}
+
+// Geometry of one lane's slots.
+struct LaneGeom {
+    double xb;      // cell index of slot 0 as a double (negative inside the pad)
+    double gdL;     // gamma * dL
+    int npad;       // pad slots in this lane (slots k < npad hold the ghost)
+};
+
+// face weight of the face right of slot k: 1 + gamma*max(L_face, 0)
+__device__ __forceinline__ double face_weight(const LaneGeom& g, int k) {
+    return fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0);
+}
+
+// One Runge-Kutta stage on the wavefront's cells:
+//   v = u + c (H_{i-1/2} - H_{i+1/2}),   u <- first ? v : wa*u0 + wb*v
+// with c = dt*G0/dL.  Returns this lane's last face value (lane 63: L_max).
+template <int K, int SCHEME>
+__device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K], LaneGeom g, double c,
+                                            double ghost, double wa, double wb, bool first) {
+    // recompute the face weights in every stage instead of keeping K of them live
+    asm volatile("" : "+v"(g.xb));
+    const double uL = shift_from_left(u[K - 1], ghost);
+    const double uR = shift_from_right(u[0], 0.0);
+    const double Hlast = face_value<SCHEME>(K >= 2 ? u[K >= 2 ? K - 2 : 0] : uL, u[K - 1], uR,
+                                            face_weight(g, K - 1), c);
+    const double HL = shift_from_left(Hlast, ghost);
+    double Hprev = HL, um1 = uL;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double up1 = (k + 1 < K) ? u[k + 1 < K ? k + 1 : 0] : uR;
+        const double H = (k == K - 1) ? Hlast : face_value<SCHEME>(um1, u[k], up1, face_weight(g, k), c);
+        const double v = u[k] + c * (Hprev - H);
+        double old = u[k];
+        u[k] = first ? v : wa * u0[k] + wb * v;
+        // Sliding-window order: the next face reads the old u[k] only after
+        // the new u[k] exists, so the scheduler cannot compute every face
+        // value up front (that keeps K extra doubles live and spills).
+        asm volatile("" : "+v"(old) : "v"(u[k]));
+        um1 = old;
+        Hprev = H;
+    }
+    return Hlast;
+}
+
+// Full time step with frozen rates.  Returns the stage-weighted face value at
+// L_max (meaningful on lane 63) so outflow = dt*G0*that.
+template <int K, int SCHEME>
+__device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, double c, double ghost) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k < g.npad) u[k] = ghost;
+    if (SCHEME == PBE_SCHEME_LW_TVD) {
+        double u0[K];
+        return fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.0, 1.0, true);
+    }
+    double u0[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u0[k] = u[k];
+    const double h0 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.0, 1.0, true);
+    const double h1 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.75, 0.25, false);
+    const double h2 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false);
+    return h0 / 6.0 + h1 / 6.0 + (2.0 / 3.0) * h2;
+}
+
+// this lane's part of sum_i L_i^3 f_i (cell centres; pad slots weigh 0)
+template <int K>
+__device__ __forceinline__ double lane_moment3(const double (&u)[K], const LaneGeom& g, double dL) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double L = fmax(g.xb + (double)k + 0.5, 0.0) * dL;
+        s = fma(L * L * L, u[k], s);
+    }
+    return s;
+}
+
+template <int K>
+__device__ __forceinline__ void lane_moments(const double (&u)[K], const LaneGeom& g, double dL, double m[4]) {
+    m[0] = m[1] = m[2] = m[3] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double x = g.xb + (double)k + 0.5;
+        const double L = fmax(x, 0.0) * dL;
+        const double f = x > 0.0 ? u[k] : 0.0;
+        m[0] += f;
+        m[1] = fma(L, f, m[1]);
+        m[2] = fma(L * L, f, m[2]);
+        m[3] = fma(L * L * L, f, m[3]);
+    }
+}
+
+}  // namespace dev
+}  // namespace pbe

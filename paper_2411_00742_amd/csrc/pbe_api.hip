@@ -1,0 +1,493 @@
+// Host side of the C ABI declared in include/pbe.h: validation, device
+// memory, launch ordering of the persistent kernels, graph capture, outputs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "pbe.h"
+#include "pbe_internal.h"
+
+using namespace pbe;
+
+namespace {
+
+struct Alloc {
+    std::vector<void*> ptrs;
+    bool ok = true;
+    template <class T>
+    T* get(size_t n) {
+        if (!ok) return nullptr;
+        void* p = nullptr;
+        if (n == 0) n = 1;
+        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+            ok = false;
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        return static_cast<T*>(p);
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+};
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+double solubility(const pbe_problem* p, double T) {
+    return p->sol_law == PBE_SOL_EXP ? p->cs0 * std::exp(p->cs1 * T) : p->cs0 + p->cs1 * T;
+}
+
+}  // namespace
+
+struct pbe_handle {
+    pbe_problem p{};                 // scalars; pointer fields are not kept
+    hipStream_t user = nullptr;      // caller's stream: work is ordered after/before it with events
+    hipStream_t stream = nullptr;    // handle-owned stream the work (and graph capture) runs on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int S = 0, ns = 0;
+    int64_t total = 0;
+    std::vector<int32_t> ncell;
+    std::vector<int64_t> off;
+    int cls_begin[kFvmClasses] = {}, cls_count[kFvmClasses] = {}, cls_blocks[kFvmClasses] = {};
+    hipStream_t side[kFvmClasses] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kFvmClasses] = {};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_g0 = nullptr, ev_g1 = nullptr;
+    bool timed_solve = false, timed_grad = false;
+    Alloc mem;
+    Fvm1dArgs a{};
+    int32_t* d_queue = nullptr;      // one work counter per class
+    double* d_gpar = nullptr;
+    double* d_tape = nullptr;
+    double* d_tapeC = nullptr;
+    double* d_tapeT = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool fresh = true;               // next pbe_step starts from the initial condition
+    bool solved = false;             // a complete pbe_solve with checkpoints exists
+};
+
+namespace {
+
+int validate(const pbe_problem* p) {
+    if (!p) return PBE_EINVAL;
+    if (p->ndim != 1) return p->ndim == 2 ? PBE_EUNSUPPORTED : PBE_EINVAL;
+    if (p->n_sims < 1 || !p->n_cells || !p->L_max || !p->f0 || !p->C0 || !p->par || !p->t_samples) return PBE_EINVAL;
+    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return p->law == PBE_LAW_MLP ? PBE_EUNSUPPORTED : PBE_EINVAL;
+    if (p->scheme != PBE_SCHEME_SSPRK3 && p->scheme != PBE_SCHEME_LW_TVD) return PBE_EINVAL;
+    if (p->sol_law != PBE_SOL_LINEAR && p->sol_law != PBE_SOL_EXP) return PBE_EINVAL;
+    if (!is_finite(p->cs0) || !is_finite(p->cs1) || !is_finite(p->alpha) || p->alpha < 0.0) return PBE_EINVAL;
+    if (!(p->cfl > 0.0 && p->cfl <= 1.0) || !(p->dt_max > 0.0) || !is_finite(p->dt_max)) return PBE_EINVAL;
+    if (!(p->t_end > 0.0) || !is_finite(p->t_end)) return PBE_EINVAL;
+    if (p->n_samples < 1) return PBE_EINVAL;
+    for (int q = 0; q < p->n_samples; ++q) {
+        const double tq = p->t_samples[q];
+        if (!is_finite(tq) || !(tq > 0.0) || tq > p->t_end) return PBE_EINVAL;
+        if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
+    }
+    if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
+    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F)) return PBE_EINVAL;
+    int64_t total = 0;
+    for (int s = 0; s < p->n_sims; ++s) {
+        const int n = p->n_cells[s];
+        if (n < 4 || n > kWave * kMaxCellsPerLane) return PBE_EINVAL;
+        if (!is_finite(p->L_max[s]) || !(p->L_max[s] > 0.0)) return PBE_EINVAL;
+        if (!is_finite(p->C0[s]) || !(p->C0[s] > 0.0)) return PBE_EINVAL;
+        const double* q = p->par + (size_t)s * PBE_NPAR;
+        for (int k = 0; k < PBE_NPAR; ++k)
+            if (!is_finite(q[k])) return PBE_EINVAL;
+        if (q[PBE_P_KG] < 0.0 || q[PBE_P_KB] < 0.0 || !(q[PBE_P_G] > 0.0) || !(q[PBE_P_B] > 0.0) ||
+            q[PBE_P_GAMMA] < 0.0 || q[PBE_P_TRAMP] < 0.0)
+            return PBE_EINVAL;
+        if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0)) return PBE_EINVAL;
+        if (!(solubility(p, q[PBE_P_T0]) > 0.0) || !(solubility(p, q[PBE_P_T1]) > 0.0)) return PBE_EINVAL;
+        total += n;
+    }
+    for (int64_t i = 0; i < total; ++i)
+        if (!is_finite(p->f0[i]) || p->f0[i] < 0.0) return PBE_EINVAL;
+    return PBE_OK;
+}
+
+// Upper bound on a sim's step count: the step can only shrink below dt_max
+// through the CFL limit, and G is bounded by the largest supersaturation the
+// solute inventory C + alpha*mu3 allows at the lowest solubility.
+double step_bound(const pbe_problem* p, int s, const double* f0) {
+    const double* q = p->par + (size_t)s * PBE_NPAR;
+    const int n = p->n_cells[s];
+    const double dL = p->L_max[s] / n;
+    double mu3 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double L = (i + 0.5) * dL;
+        mu3 += L * L * L * f0[i] * dL;
+    }
+    const double csat_min = std::min(solubility(p, q[PBE_P_T0]), solubility(p, q[PBE_P_T1]));
+    const double Smax = std::max(0.0, (p->C0[s] + p->alpha * mu3) / csat_min - 1.0);
+    const double Gmax = 1e6 * q[PBE_P_KG] * std::pow(Smax, q[PBE_P_G]) * (1.0 + q[PBE_P_GAMMA] * p->L_max[s]);
+    double dt_min = p->dt_max;
+    if (Gmax > 0.0) dt_min = std::min(dt_min, p->cfl * dL / Gmax);
+    return p->t_end / dt_min + p->n_samples + 2.0;
+}
+
+int fail(pbe_handle* h, int code) {
+    pbe_destroy(h);
+    return code;
+}
+
+#define HIP_OK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return PBE_EDEVICE; \
+    } while (0)
+
+int launch_classes(pbe_handle* h, int from_initial, int max_steps) {
+    h->a.from_initial = from_initial;
+    h->a.max_steps = max_steps;
+    HIP_OK(launch_reset_counter(h->d_queue, kFvmClasses, h->stream));
+    HIP_OK(hipEventRecord(h->ev_fork, h->stream));
+    for (int c = 0; c < kFvmClasses; ++c) {
+        if (h->cls_count[c] == 0) continue;
+        hipStream_t st = c == 0 ? h->stream : h->side[c];
+        if (c != 0) HIP_OK(hipStreamWaitEvent(st, h->ev_fork, 0));
+        HIP_OK(launch_fvm1d_class(c, h->a, h->cls_blocks[c], h->cls_begin[c], h->cls_count[c], h->d_queue + c, st));
+        if (c != 0) {
+            HIP_OK(hipEventRecord(h->ev_join[c], st));
+            HIP_OK(hipStreamWaitEvent(h->stream, h->ev_join[c], 0));
+        }
+    }
+    return PBE_OK;
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int fill(double* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return PBE_OK;
+    const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, p, n, 0.0);
+    HIP_OK(hipGetLastError());
+    return PBE_OK;
+}
+
+int clear_samples(pbe_handle* h) {
+    int rc = fill(h->a.mom_s, (int64_t)h->S * h->ns * 4, h->stream);
+    if (rc == PBE_OK) rc = fill(h->a.C_s, (int64_t)h->S * h->ns, h->stream);
+    if (rc == PBE_OK && h->a.record_f) rc = fill(h->a.f_s, h->total * h->ns, h->stream);
+    return rc;
+}
+
+// order the handle's stream after everything already queued on the caller's stream
+int enter(pbe_handle* h) {
+    HIP_OK(hipEventRecord(h->ev_in, h->user));
+    HIP_OK(hipStreamWaitEvent(h->stream, h->ev_in, 0));
+    return PBE_OK;
+}
+// and the caller's stream after the handle's work
+int leave(pbe_handle* h) {
+    HIP_OK(hipEventRecord(h->ev_out, h->stream));
+    HIP_OK(hipStreamWaitEvent(h->user, h->ev_out, 0));
+    return PBE_OK;
+}
+
+int copy_out(pbe_handle* h, void* dst, const void* src, size_t bytes) {
+    if (!dst || bytes == 0) return PBE_OK;
+    if (h->p.flags & PBE_FLAG_DEVICE_PTRS) {
+        HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    }
+    return PBE_OK;
+}
+
+int write_outputs(pbe_handle* h, double* f_out, double* mom_out, double* C_out, int32_t* steps_out,
+                  int32_t* status_out) {
+    int rc = PBE_OK;
+    if (h->a.record_f)
+        rc = copy_out(h, f_out, h->a.f_s, sizeof(double) * h->total * h->ns);
+    else
+        rc = copy_out(h, f_out, h->a.f, sizeof(double) * h->total);
+    if (rc == PBE_OK) rc = copy_out(h, mom_out, h->a.mom_s, sizeof(double) * (size_t)h->S * h->ns * 4);
+    if (rc == PBE_OK) rc = copy_out(h, C_out, h->a.C_s, sizeof(double) * (size_t)h->S * h->ns);
+    if (rc == PBE_OK) rc = copy_out(h, steps_out, h->a.step, sizeof(int32_t) * h->S);
+    if (rc == PBE_OK) rc = copy_out(h, status_out, h->a.status, sizeof(int32_t) * h->S);
+    if (rc == PBE_OK) rc = leave(h);
+    if (rc == PBE_OK && !(h->p.flags & PBE_FLAG_DEVICE_PTRS)) HIP_OK(hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pbe_strerror(int code) {
+    switch (code) {
+        case PBE_OK: return "ok";
+        case PBE_EINVAL: return "invalid argument";
+        case PBE_ENOMEM: return "device memory allocation failed";
+        case PBE_EDEVICE: return "HIP runtime error";
+        case PBE_ENONFINITE: return "non-finite state";
+        case PBE_ESTATE: return "call not valid in the handle's current state";
+        case PBE_EUNSUPPORTED: return "unsupported option combination";
+        default: return "unknown status code";
+    }
+}
+
+int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
+    if (!out) return PBE_EINVAL;
+    *out = nullptr;
+    const int v = validate(p);
+    if (v != PBE_OK) return v;
+    pbe_handle* h = new (std::nothrow) pbe_handle();
+    if (!h) return PBE_ENOMEM;
+    h->p = *p;
+    h->p.n_cells = nullptr; h->p.L_max = nullptr; h->p.f0 = nullptr; h->p.C0 = nullptr;
+    h->p.par = nullptr; h->p.mlp = nullptr; h->p.t_samples = nullptr;
+    h->user = static_cast<hipStream_t>(hip_stream);
+    h->S = p->n_sims;
+    h->ns = p->n_samples;
+    h->ncell.assign(p->n_cells, p->n_cells + h->S);
+    h->off.assign(h->S + 1, 0);
+    for (int s = 0; s < h->S; ++s) h->off[s + 1] = h->off[s] + h->ncell[s];
+    h->total = h->off[h->S];
+
+    // step budget and launch order: class by cells per lane, longest first within a class
+    std::vector<double> bound(h->S), cost(h->S);
+    double cap = 0.0;
+    for (int s = 0; s < h->S; ++s) {
+        bound[s] = step_bound(p, s, p->f0 + h->off[s]);
+        cap = std::max(cap, bound[s]);
+        const double* q = p->par + (size_t)s * PBE_NPAR;
+        const double dL = p->L_max[s] / h->ncell[s];
+        const double Sg = std::max(0.0, p->C0[s] / solubility(p, q[PBE_P_T1]) - 1.0) * 0.5;
+        const double G = 1e6 * q[PBE_P_KG] * std::pow(Sg, q[PBE_P_G]) * (1.0 + 0.5 * q[PBE_P_GAMMA] * p->L_max[s]);
+        const double dt = G > 0.0 ? std::min(p->dt_max, p->cfl * dL / G) : p->dt_max;
+        cost[s] = (double)h->ncell[s] * (p->t_end / dt);
+    }
+    int step_cap = p->max_steps > 0 ? p->max_steps : (int)std::min(1.0e9, std::ceil(cap * 1.05) + 8.0);
+    std::vector<int32_t> order(h->S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int cx = fvm1d_class_of(h->ncell[x]), cy = fvm1d_class_of(h->ncell[y]);
+        if (cx != cy) return cx < cy;
+        return cost[x] > cost[y];
+    });
+    for (int c = 0; c < kFvmClasses; ++c) h->cls_count[c] = 0;
+    for (int s = 0; s < h->S; ++s) h->cls_count[fvm1d_class_of(h->ncell[s])]++;
+    h->cls_begin[0] = 0;
+    for (int c = 1; c < kFvmClasses; ++c) h->cls_begin[c] = h->cls_begin[c - 1] + h->cls_count[c - 1];
+
+    // device memory
+    Alloc& m = h->mem;
+    Fvm1dArgs& a = h->a;
+    const int S = h->S, ns = h->ns;
+    a.n_sims = S;
+    a.n_samples = ns;
+    a.law = p->law; a.scheme = p->scheme; a.sol_law = p->sol_law;
+    a.record_f = (p->flags & PBE_FLAG_RECORD_F) ? 1 : 0;
+    a.cs0 = p->cs0; a.cs1 = p->cs1; a.alpha = p->alpha; a.cfl = p->cfl; a.dt_max = p->dt_max; a.t_end = p->t_end;
+    double* d_ts = m.get<double>(ns);
+    int32_t* d_order = m.get<int32_t>(S);
+    h->d_queue = m.get<int32_t>(kFvmClasses);
+    int64_t* d_off = m.get<int64_t>(S + 1);
+    int32_t* d_ncell = m.get<int32_t>(S);
+    double* d_Lmax = m.get<double>(S);
+    double* d_par = m.get<double>((size_t)S * PBE_NPAR);
+    double* d_C0 = m.get<double>(S);
+    double* d_f0 = m.get<double>(h->total);
+    a.f = m.get<double>(h->total);
+    a.C = m.get<double>(S); a.t = m.get<double>(S); a.mu3 = m.get<double>(S); a.outflow = m.get<double>(S);
+    a.step = m.get<int32_t>(S); a.next = m.get<int32_t>(S); a.status = m.get<int32_t>(S);
+    a.mom_s = m.get<double>((size_t)S * ns * 4);
+    a.C_s = m.get<double>((size_t)S * ns);
+    a.samp_step = m.get<int32_t>((size_t)S * ns);
+    a.f_s = a.record_f ? m.get<double>((size_t)h->total * ns) : nullptr;
+    a.ckpt_every = p->ckpt_every;
+    a.n_ckpt = 0;
+    if (p->ckpt_every > 0) {
+        a.n_ckpt = step_cap / p->ckpt_every + 2;
+        a.ck_f = m.get<double>((size_t)h->total * a.n_ckpt);
+        a.ck_C = m.get<double>((size_t)S * a.n_ckpt);
+        a.ck_t = m.get<double>((size_t)S * a.n_ckpt);
+        h->d_gpar = m.get<double>((size_t)S * PBE_NGRAD);
+    }
+    if (!m.ok) return fail(h, PBE_ENOMEM);
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) != hipSuccess)
+        return fail(h, PBE_EDEVICE);
+    a.t_samples = d_ts; a.order = d_order; a.off = d_off; a.ncell = d_ncell; a.Lmax = d_Lmax; a.par = d_par;
+    a.C0 = d_C0; a.f0 = d_f0;
+    a.step_cap = step_cap;
+
+    if (hipMemcpy(d_ts, p->t_samples, sizeof(double) * ns, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_order, order.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_off, h->off.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_ncell, p->n_cells, sizeof(int32_t) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_Lmax, p->L_max, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_par, p->par, sizeof(double) * S * PBE_NPAR, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_C0, p->C0, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(h, PBE_EDEVICE);
+
+    for (int c = 0; c < kFvmClasses; ++c) {
+        const int resident = fvm1d_class_resident_blocks(c);
+        if (resident <= 0) return fail(h, PBE_EDEVICE);
+        h->cls_blocks[c] = std::max(1, std::min(h->cls_count[c], resident));
+        if (c > 0 && hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking) != hipSuccess)
+            return fail(h, PBE_EDEVICE);
+        if (hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming) != hipSuccess) return fail(h, PBE_EDEVICE);
+    }
+    if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess ||
+        hipEventCreate(&h->ev_g0) != hipSuccess || hipEventCreate(&h->ev_g1) != hipSuccess)
+        return fail(h, PBE_EDEVICE);
+    *out = h;
+    return PBE_OK;
+}
+
+int pbe_reset(pbe_handle* h) {
+    if (!h) return PBE_EINVAL;
+    h->fresh = true;
+    h->solved = false;
+    return PBE_OK;
+}
+
+int pbe_step(pbe_handle* h, int32_t n_steps, int32_t* n_active_out) {
+    if (!h || n_steps < 0) return PBE_EINVAL;
+    int rc = enter(h);
+    if (rc == PBE_OK && h->fresh) rc = clear_samples(h);
+    if (rc == PBE_OK) rc = launch_classes(h, h->fresh ? 1 : 0, n_steps);
+    if (rc == PBE_OK) rc = leave(h);
+    if (rc != PBE_OK) return rc;
+    h->fresh = false;
+    h->solved = false;
+    if (n_active_out) {
+        std::vector<double> t(h->S);
+        std::vector<int32_t> st(h->S);
+        HIP_OK(hipMemcpyAsync(t.data(), h->a.t, sizeof(double) * h->S, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipMemcpyAsync(st.data(), h->a.status, sizeof(int32_t) * h->S, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+        int active = 0;
+        for (int s = 0; s < h->S; ++s)
+            if (t[s] < h->p.t_end && !(st[s] & (PBE_SIM_NONFINITE | PBE_SIM_STEPCAP))) ++active;
+        *n_active_out = active;
+    }
+    return PBE_OK;
+}
+
+int pbe_solve(pbe_handle* h, double* f_out, double* mom_out, double* C_out, int32_t* steps_out,
+              int32_t* status_out) {
+    if (!h) return PBE_EINVAL;
+    if (!h->graph_exec) {
+        // one graph: clear samples, reset queues, fork the class kernels, join
+        if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PBE_EDEVICE;
+        int rc = clear_samples(h);
+        if (rc == PBE_OK) rc = launch_classes(h, 1, std::numeric_limits<int32_t>::max());
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (rc != PBE_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != PBE_OK ? rc : PBE_EDEVICE;
+        }
+        if (hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            h->graph_exec = nullptr;
+            return PBE_EDEVICE;
+        }
+        h->graph = g;
+    }
+    if (enter(h) != PBE_OK) return PBE_EDEVICE;
+    HIP_OK(hipEventRecord(h->ev_t0, h->stream));
+    HIP_OK(hipGraphLaunch(h->graph_exec, h->stream));
+    HIP_OK(hipEventRecord(h->ev_t1, h->stream));
+    h->timed_solve = true;
+    h->fresh = false;
+    h->solved = h->p.ckpt_every > 0;
+    return write_outputs(h, f_out, mom_out, C_out, steps_out, status_out);
+}
+
+int pbe_fetch(pbe_handle* h, double* f_out, double* mom_out, double* C_out, int32_t* steps_out,
+              int32_t* status_out) {
+    if (!h) return PBE_EINVAL;
+    if (h->fresh) return PBE_ESTATE;
+    if (enter(h) != PBE_OK) return PBE_EDEVICE;
+    return write_outputs(h, f_out, mom_out, C_out, steps_out, status_out);
+}
+
+int pbe_set_par(pbe_handle* h, const double* par) {
+    if (!h || !par) return PBE_EINVAL;
+    for (int64_t i = 0; i < (int64_t)h->S * PBE_NPAR; ++i)
+        if (!is_finite(par[i])) return PBE_EINVAL;
+    for (int s = 0; s < h->S; ++s) {
+        const double* q = par + (size_t)s * PBE_NPAR;
+        if (q[PBE_P_KG] < 0.0 || q[PBE_P_KB] < 0.0 || !(q[PBE_P_G] > 0.0) || !(q[PBE_P_B] > 0.0) ||
+            q[PBE_P_GAMMA] < 0.0 || q[PBE_P_TRAMP] < 0.0)
+            return PBE_EINVAL;
+    }
+    // the previous launches may still read the parameters: wait for them first
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpy(const_cast<double*>(h->a.par), par, sizeof(double) * h->S * PBE_NPAR, hipMemcpyHostToDevice));
+    h->fresh = true;
+    h->solved = false;
+    return PBE_OK;
+}
+
+int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
+             float* gmlp_out) {
+    (void)gf; (void)gmom; (void)gC; (void)gpar_out; (void)gmlp_out;
+    if (!h) return PBE_EINVAL;
+    if (h->p.ckpt_every <= 0 || !h->solved) return PBE_ESTATE;
+    return PBE_EUNSUPPORTED;
+}
+
+int pbe_last_kernel_ms(pbe_handle* h, float* solve_ms, float* grad_ms) {
+    if (!h) return PBE_EINVAL;
+    if (solve_ms) {
+        *solve_ms = -1.0f;
+        if (h->timed_solve) {
+            HIP_OK(hipEventSynchronize(h->ev_t1));
+            HIP_OK(hipEventElapsedTime(solve_ms, h->ev_t0, h->ev_t1));
+        }
+    }
+    if (grad_ms) {
+        *grad_ms = -1.0f;
+        if (h->timed_grad) {
+            HIP_OK(hipEventSynchronize(h->ev_g1));
+            HIP_OK(hipEventElapsedTime(grad_ms, h->ev_g0, h->ev_g1));
+        }
+    }
+    return PBE_OK;
+}
+
+void pbe_destroy(pbe_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (int c = 0; c < kFvmClasses; ++c) {
+        if (h->side[c]) {
+            (void)hipStreamSynchronize(h->side[c]);
+            (void)hipStreamDestroy(h->side[c]);
+        }
+        if (h->ev_join[c]) (void)hipEventDestroy(h->ev_join[c]);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    if (h->ev_t0) (void)hipEventDestroy(h->ev_t0);
+    if (h->ev_t1) (void)hipEventDestroy(h->ev_t1);
+    if (h->ev_g0) (void)hipEventDestroy(h->ev_g0);
+    if (h->ev_g1) (void)hipEventDestroy(h->ev_g1);
+    h->mem.release();
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+}  // extern "C"

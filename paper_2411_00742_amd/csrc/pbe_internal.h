@@ -1,0 +1,81 @@
+// Internal kernel argument blocks and launchers shared by the host library
+// (pbe_api.cpp) and the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pbe.h"
+
+namespace pbe {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxCellsPerLane = 32;  // 1D grids up to 64*32 = 2048 cells per wavefront
+
+// Everything the 1D forward kernel reads or writes.  Device pointers only.
+struct Fvm1dArgs {
+    int32_t n_sims, n_samples;
+    int32_t law, scheme, sol_law, record_f;
+    double cs0, cs1, alpha, cfl, dt_max, t_end;
+    const double* t_samples;   // [n_samples]
+    const int32_t* order;      // [S] sims in launch order (longest first)
+    int32_t* queue;            // work counter, zeroed before each launch
+    const int64_t* off;        // [S+1] packed cell offsets
+    const int32_t* ncell;      // [S]
+    const double* Lmax;        // [S]
+    const double* par;         // [S*PBE_NPAR]
+    const double* C0;          // [S]
+    const double* f0;          // [sum N] initial densities
+    // running state (resumable between launches)
+    double* f;                 // [sum N]
+    double* C;                 // [S]
+    double* t;                 // [S]
+    double* mu3;               // [S] volume moment of the current state
+    double* outflow;           // [S] number that left through L_max
+    int32_t* step;             // [S]
+    int32_t* next;             // [S] index of the next sample time
+    int32_t* status;           // [S] PBE_SIM_* bits
+    // recorded samples
+    double* mom_s;             // [S][n_samples][4]
+    double* C_s;               // [S][n_samples]
+    double* f_s;               // [sum N * n_samples] (record_f) sim-major
+    int32_t* samp_step;        // [S][n_samples] step index at which each sample was taken
+    // checkpoints of (f, C, t) every ckpt_every steps
+    double* ck_f;              // [sum N * n_ckpt]
+    double* ck_C;              // [S * n_ckpt]
+    double* ck_t;              // [S * n_ckpt]
+    int32_t ckpt_every, n_ckpt;
+    int32_t max_steps;         // steps allowed in this launch
+    int32_t from_initial;      // 1: start from (f0, C0, t = 0)
+    int32_t step_cap;          // absolute per-sim step limit (PBE_SIM_STEPCAP when hit)
+    int32_t pad_;
+};
+
+// Adjoint of the 1D solve (reverse sweep over checkpointed segments).
+struct Adj1dArgs {
+    Fvm1dArgs fw;              // forward description (state buffers are read-only here)
+    const double* gf;          // cotangent of the recorded f (or final f), may be null
+    const double* gmom;        // [S][n_samples][4], may be null
+    const double* gC;          // [S][n_samples], may be null
+    double* gpar;              // [S][PBE_NGRAD] output
+    double* tape;              // [sum N * ckpt_every] per-sim segment tape of states
+    double* tape_C;            // [S * ckpt_every]
+    double* tape_t;            // [S * ckpt_every]
+    int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
+    int32_t pad_;
+};
+
+// Launchers (defined in the .hip files).  Return hipSuccess or the launch error.
+constexpr int kFvmClasses = 4;   // kernel classes by cells per lane: 1-8, 9-16, 17-24, 25-32
+inline int fvm1d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
+hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* queue,
+                              hipStream_t st);
+hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st);
+int fvm1d_class_resident_blocks(int cls);
+hipError_t launch_adj1d(const Adj1dArgs& a, int n_blocks, hipStream_t st);
+int adj1d_max_resident_blocks();
+
+}  // namespace pbe
+
+// extra per-sim status bit used internally and reported through status_out
+#define PBE_SIM_STEPCAP 8
