@@ -193,3 +193,37 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class PBESolve(torch.autograd.Function):
+        """Differentiable batched solve: kinetics (kg, g, kb, b, gamma) per sim -> recorded outputs.
+
+        forward(par5 [S, 5] float64, solver) -> (f, mom, C); backward runs the
+        library's discrete adjoint (pbe_grad) with the solve's step schedule held
+        fixed.  The solver must have been created with ckpt_every > 0.
+        """
+
+        @staticmethod
+        def forward(ctx, par5, solver):
+            par = np.array(solver.prob.par, dtype=np.float64, copy=True)
+            par[:, :NGRAD] = par5.detach().cpu().numpy()
+            solver.set_par(par)
+            out = solver.solve()
+            ctx.solver = solver
+            ctx.par_device = par5.device
+            return out["f"], out["mom"], out["C"]
+
+        @staticmethod
+        def backward(ctx, gf, gmom, gC):
+            g = ctx.solver.grad(gf, gmom, gC)
+            return g.to(ctx.par_device), None
+
+    return PBESolve
+
+
+def pbe_solve_autograd(par5, solver):
+    """Apply the differentiable solve (see PBESolve)."""
+    return _autograd_function().apply(par5, solver)

@@ -1,0 +1,363 @@
+// Discrete adjoint of the batched 1D solve (gfx950, FP64).
+//
+// Reverse-mode derivative of the recorded outputs (samples of f, mu_0..mu_3
+// and C) with respect to each simulation's (kg, g, kb, b, gamma), with the
+// forward step-size schedule held fixed.  The paper obtains such gradients
+// by reverse-mode AD with checkpointing (Sec. 4.1, SI S2.1); here the adjoint
+// of the time loop is written by hand.
+//
+// One wavefront per simulation, same register layout as the forward kernel.
+// For each checkpoint segment (ckpt_every steps), last to first:
+//   1. reload the checkpoint (f, C, t) and recompute the segment forward with
+//      the forward kernel's step, writing the state at each step to a tape;
+//   2. walk the segment backwards: for step m-1 -> m, recompute the three
+//      SSP-RK3 stage states on-chip from the taped f^{m-1}, then apply the
+//      transposed Jacobians of the stages, the solute balance (Eq. (9)) and
+//      the rate laws, adding sample cotangents as their steps are reached.
+// Derivative conventions: the limited slope psi = 2ab/(a+b) for ab > 0 has
+// zero derivative where ab <= 0; max(S, 0) and S^p have zero derivative at S <= 0.
+#include "fvm1d_device.h"
+#include "pbe_internal.h"
+
+namespace pbe {
+namespace {
+
+using namespace dev;
+
+// Adjoint of one stage v_i = u_i + c (H_{i-1/2} - H_{i+1/2}) taken at the stage
+// input u.  On entry ub holds vbar (adjoint of v); on exit ub holds ubar.
+// Accumulates per lane: cbar (adjoint of c), gbar (adjoint of the inflow
+// ghost value, lane 0 only) and gam (adjoint of gamma through the face weights).
+template <int K>
+__device__ __forceinline__ void adj_stage(const double* __restrict__ us, double (&ub)[K], LaneGeom g, double c,
+                                          double ghost, int lane, double& cbar, double& gbar, double& gam, double dL) {
+    asm volatile("" : "+v"(g.xb));
+    // us: this stage's input state in LDS, slot k of this lane at us[k * 64 + lane]
+    const double uL = shift_from_left(us[(K - 1) * 64 + lane], ghost);
+    const double uR = shift_from_right(us[lane], 0.0);
+    const double vbR = shift_from_right(ub[0], 0.0);   // vbar of the cell right of this lane (none past L_max)
+    const double vb0 = ub[0];
+    // leftmost face of the wave (left of lane 0, slot 0) carries H = ghost
+    if (lane == 0) {
+        cbar = fma(ghost, vb0, cbar);
+        gbar = fma(c, vb0, gbar);
+    }
+    double send_left = 0.0;   // -abar of slot 0: belongs to the left neighbour's last cell
+    double carry = 0.0;       // bbar of slot k-1 to add to slot k
+    double vbk = vb0;         // original vbar_k
+    double um1 = uL;
+    double uk = us[lane];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double up1 = (k + 1 < K) ? us[(k + 1) * 64 + lane] : uR;
+        const double vbk1 = (k + 1 < K) ? ub[k + 1 < K ? k + 1 : 0] : vbR;   // still original here
+        const double a = uk - um1, b = up1 - uk;
+        const double p = a * b;
+        const bool same = p > 0.0;
+        const double s = same ? a + b : 1.0;
+        const double r = 1.0 / s;
+        const double psi = same ? (p + p) * r : 0.0;
+        const double r2 = 2.0 * r * r;
+        const double psia = same ? b * b * r2 : 0.0;
+        const double psib = same ? a * a * r2 : 0.0;
+        const double Lf = fmax(g.xb + (double)(k + 1), 0.0) * dL;
+        const double w = fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0);
+        const double face = uk + 0.5 * psi;
+        const double H = w * face;
+        const double dv = vbk1 - vbk;
+        cbar = fma(H, dv, cbar);
+        const double Hb = c * dv;
+        gam = fma(Hb * face, Lf, gam);
+        const double pb = 0.5 * Hb * w;
+        const double ab = pb * psia;
+        const double bb = pb * psib;
+        // ubar_k = vbar_k (direct term) + face terms + what slot k-1 pushed right
+        const double ubk = vbk + Hb * w + ab - bb + carry;
+        if (k == 0) {
+            send_left = -ab;
+        } else {
+            ub[k >= 1 ? k - 1 : 0] -= ab;
+        }
+        ub[k] = ubk;
+        carry = bb;
+        vbk = vbk1;
+        // sliding-window order (see fvm_stage): the next slot starts after this one
+        double next_um1 = uk;
+        asm volatile("" : "+v"(next_um1) : "v"(ubk));
+        um1 = next_um1;
+        uk = up1;
+    }
+    // bbar of the last slot goes to the right neighbour's slot 0; -abar of
+    // slot 0 to the left neighbour's last slot (lane 0: to the ghost)
+    const double from_left = shift_from_left(carry, 0.0);
+    const double from_right = shift_from_right(send_left, 0.0);
+    ub[0] += from_left;
+    ub[K - 1] += from_right;
+    if (lane == 0) gbar += send_left;
+}
+
+template <int K>
+__device__ __forceinline__ void set_pad(double (&u)[K], const LaneGeom& g, double v) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = k < g.npad ? v : u[k];
+}
+
+template <int K>
+__device__ __forceinline__ void stage_fwd(double (&u)[K], const double (&u0)[K], const LaneGeom& g, double c,
+                                          double ghost, double wa, double wb, bool first) {
+    (void)fvm_stage<K, PBE_SCHEME_SSPRK3>(u, u0, g, c, ghost, wa, wb, first);
+}
+
+__device__ __forceinline__ int samples_reached(const double* ts, int ns, double t) {
+    int n = 0;
+    for (int q = 0; q < ns; ++q) n += (ts[q] <= t) ? 1 : 0;
+    return uniform(n);
+}
+
+template <int K>
+__device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* __restrict__ lds) {
+    const Fvm1dArgs& a = A.fw;
+    const int lane = threadIdx.x;
+    const int N = uniform(a.ncell[s]);
+    const int64_t base = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
+    const double Lmax = uniform(a.Lmax[s]);
+    const double dL = Lmax / N;
+    const SimParams q = load_params(a.par + (size_t)s * PBE_NPAR);
+    const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
+    const int ns = a.n_samples;
+    const double* ts = a.t_samples;
+    const int Kc = a.ckpt_every;
+
+    const int pad = 64 * K - N;
+    LaneGeom g;
+    g.xb = (double)(lane * K - pad);
+    g.gdL = q.gamma * dL;
+    g.npad = min(max(pad - lane * K, 0), K);
+    const int i0 = lane * K - pad;
+
+    const int n_total = uniform(a.step[s]);
+    if (uniform(a.status[s]) & (PBE_SIM_NONFINITE | PBE_SIM_STEPCAP)) {
+        // the forward did not reach t_end: no derivative is defined
+        if (lane == 0)
+            for (int j = 0; j < PBE_NGRAD; ++j) A.gpar[(int64_t)s * PBE_NGRAD + j] = __builtin_nan("");
+        return;
+    }
+    double lam[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) lam[k] = 0.0;
+    if (A.gf && A.gf_is_final) load_cells(lam, A.gf + base, i0, g.npad, 0.0);
+    double lamC = 0.0;
+    double gk[4] = {0.0, 0.0, 0.0, 0.0};
+    double gam = 0.0;
+    int qs = ns - 1;   // next sample (from the end) whose cotangent is still to be added
+
+    double* tape = A.tape + base * Kc;
+    double* tapeC = A.tape_C + (int64_t)s * Kc;
+    double* tapeT = A.tape_t + (int64_t)s * Kc;
+
+    const int n_seg = (n_total + Kc - 1) / Kc;
+    for (int seg = n_seg - 1; seg >= 0; --seg) {
+        const int m0 = seg * Kc;
+        const int m1 = min(m0 + Kc, n_total);
+        // ---- recompute the segment forward, taping the state at each step
+        double u[K];
+        load_cells(u, a.ck_f + base * a.n_ckpt + (int64_t)seg * N, i0, g.npad, 0.0);
+        double C = uniform(a.ck_C[(int64_t)s * a.n_ckpt + seg]);
+        double t = uniform(a.ck_t[(int64_t)s * a.n_ckpt + seg]);
+        int next = samples_reached(ts, ns, t);
+        LaneGeom gm = g;
+        asm volatile("" : "+v"(gm.xb));
+        double mu3_old = wave_sum(lane_moment3(u, gm, dL)) * dL;
+        for (int m = m0; m < m1; ++m) {
+            store_cells(u, tape + (int64_t)(m - m0) * N, i0, g.npad);
+            if (lane == 0) {
+                tapeC[m - m0] = C;
+                tapeT[m - m0] = t;
+            }
+            const Rates r = rates_plain(p, q, C, t);
+            const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
+            double dt;
+            const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
+            const double ghost = r.G0 > 0.0 ? r.B / r.G0 : 0.0;
+            (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, dt * r.G0 / dL, ghost);
+            LaneGeom g2 = g;
+            asm volatile("" : "+v"(g2.xb));
+            const double mu3 = wave_sum(lane_moment3(u, g2, dL)) * dL;
+            C = uniform(C - p.alpha * (mu3 - mu3_old));
+            mu3_old = mu3;
+            t = uniform(hit ? t_next : t + dt);
+            if (hit) next = samples_reached(ts, ns, t);
+        }
+        // (each lane reads back only the tape addresses it wrote itself)
+
+        // ---- reverse walk over the segment
+        for (int m = m1; m > m0; --m) {
+            // cotangents of the samples taken at state m
+            while (qs >= 0 && a.samp_step[(int64_t)s * ns + qs] == m) {
+                const int64_t o = (int64_t)s * ns + qs;
+                const double gc = A.gC ? A.gC[o] : 0.0;
+                lamC += gc;
+                double gm4[4] = {0.0, 0.0, 0.0, 0.0};
+                if (A.gmom) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) gm4[j] = A.gmom[o * 4 + j];
+                }
+                LaneGeom g3 = g;
+                asm volatile("" : "+v"(g3.xb));
+                double gcell[K];
+                if (A.gf && !A.gf_is_final)
+                    load_cells(gcell, A.gf + base * ns + (int64_t)qs * N, i0, g.npad, 0.0);
+                else
+#pragma unroll
+                    for (int k = 0; k < K; ++k) gcell[k] = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double x = g3.xb + (double)k + 0.5;
+                    const double L = fmax(x, 0.0) * dL;
+                    const double add = ((gm4[3] * L + gm4[2]) * L + gm4[1]) * L * dL + gm4[0] * dL + gcell[k];
+                    lam[k] += x > 0.0 ? add : 0.0;
+                }
+                --qs;
+            }
+
+            // state at m-1 from the tape
+            double u0[K];
+            load_cells(u0, tape + (int64_t)(m - 1 - m0) * N, i0, g.npad, 0.0);
+            const double Cm = uniform(tapeC[m - 1 - m0]);
+            const double tm = uniform(tapeT[m - 1 - m0]);
+            const int nx = samples_reached(ts, ns, tm);
+            const Rates r = rates_plain(p, q, Cm, tm);
+            const double t_next = uniform(nx < ns ? ts[min(nx, ns - 1)] : p.t_end);
+            double dt;
+            (void)choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_next, &dt);
+            const double ghost = r.G0 > 0.0 ? r.B / r.G0 : 0.0;
+            const double c = dt * r.G0 / dL;
+
+            // stage input states u0, u1, u2 into this wave's LDS
+            set_pad(u0, g, ghost);
+            {
+                double u[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    u[k] = u0[k];
+                    lds[(0 * K + k) * 64 + lane] = u0[k];
+                }
+                stage_fwd(u, u0, g, c, ghost, 0.0, 1.0, true);
+#pragma unroll
+                for (int k = 0; k < K; ++k) lds[(1 * K + k) * 64 + lane] = u[k];
+                stage_fwd(u, u0, g, c, ghost, 0.75, 0.25, false);
+#pragma unroll
+                for (int k = 0; k < K; ++k) lds[(2 * K + k) * 64 + lane] = u[k];
+            }
+
+            // solute balance: Phi's output f^m also feeds C^m = C^{m-1} - alpha (mu3(f^m) - mu3(f^{m-1}))
+            double ub[K], l0[K];
+            {
+                LaneGeom g4 = g;
+                asm volatile("" : "+v"(g4.xb));
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double L = fmax(g4.xb + (double)k + 0.5, 0.0) * dL;
+                    const double lp = lam[k] - p.alpha * lamC * (L * L * L * dL);
+                    ub[k] = (2.0 / 3.0) * lp;   // vbar of stage 3
+                    l0[k] = (1.0 / 3.0) * lp;
+                }
+            }
+            double cbar = 0.0, gbar = 0.0;
+            adj_stage<K>(lds + 2 * K * 64, ub, g, c, ghost, lane, cbar, gbar, gam, dL);   // ub = adjoint of u2
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                l0[k] = fma(0.75, ub[k], l0[k]);
+                ub[k] = 0.25 * ub[k];
+            }
+            adj_stage<K>(lds + 1 * K * 64, ub, g, c, ghost, lane, cbar, gbar, gam, dL);   // ub = adjoint of u1
+            adj_stage<K>(lds, ub, g, c, ghost, lane, cbar, gbar, gam, dL);   // ub = adjoint of u0 via stage 1
+            {
+                LaneGeom g5 = g;
+                asm volatile("" : "+v"(g5.xb));
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double l = l0[k] + ub[k];
+                    const bool padk = k < g5.npad;   // pad slots were set to the ghost at the step start
+                    const double L = fmax(g5.xb + (double)k + 0.5, 0.0) * dL;
+                    gbar += padk ? l : 0.0;
+                    lam[k] = padk ? 0.0 : fma(p.alpha * lamC, L * L * L * dL, l);
+                }
+            }
+            // rates: c = dt G0/dL, ghost = B/G0
+            const double cb = wave_sum(cbar);
+            const double gb = wave_sum(gbar);
+            double G0b = cb * dt / dL, Bb = 0.0;
+            if (r.G0 > 0.0) {
+                Bb = gb / r.G0;
+                G0b -= gb * ghost / r.G0;
+            }
+            if (r.S > 0.0) {
+                const double Csat = solubility(p, temperature(q, tm));
+                const double dGdS = q.g * r.G0 / r.S;
+                const double dBdS = q.b * r.B / r.S;
+                lamC += (G0b * dGdS + Bb * dBdS) / Csat;
+                gk[0] += G0b * 1e6 * exp64(q.g * r.lnS) * r.arrG;
+                gk[1] += G0b * r.G0 * r.lnS;
+                gk[2] += Bb * exp64(q.b * r.lnS) * r.arrB;
+                gk[3] += Bb * r.B * r.lnS;
+            }
+            lamC = uniform(lamC);
+        }
+    }
+    const double gg = wave_sum(gam);
+    if (lane == 0) {
+        double* o = A.gpar + (int64_t)s * PBE_NGRAD;
+        o[0] = gk[0]; o[1] = gk[1]; o[2] = gk[2]; o[3] = gk[3]; o[4] = gg;
+    }
+}
+
+// Adjoint classes: cells per lane 1-8 and 9-16 (grids up to 1024 cells).
+template <int KLO>
+__global__ __launch_bounds__(64) void k_adj1d(Adj1dArgs A, int cls_begin, int cls_count, int32_t* queue) {
+    // the three SSP-RK3 stage input states of the step being reversed (each lane owns its column)
+    __shared__ double lds[3 * (KLO + 7) * 64];
+    for (;;) {
+        const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
+        const int idx = __builtin_amdgcn_readfirstlane(ticket);
+        if (idx >= cls_count) break;
+        const int s = uniform(A.fw.order[cls_begin + idx]);
+        const int K = uniform((A.fw.ncell[s] + 63) >> 6);
+        switch (K - KLO) {
+            case 0: adjoint_sim<KLO + 0>(A, s, lds); break;
+            case 1: adjoint_sim<KLO + 1>(A, s, lds); break;
+            case 2: adjoint_sim<KLO + 2>(A, s, lds); break;
+            case 3: adjoint_sim<KLO + 3>(A, s, lds); break;
+            case 4: adjoint_sim<KLO + 4>(A, s, lds); break;
+            case 5: adjoint_sim<KLO + 5>(A, s, lds); break;
+            case 6: adjoint_sim<KLO + 6>(A, s, lds); break;
+            case 7: adjoint_sim<KLO + 7>(A, s, lds); break;
+            default: break;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
+                              hipStream_t st) {
+    if (cls == 0)
+        hipLaunchKernelGGL(k_adj1d<1>, dim3(n_blocks), dim3(64), 0, st, A, begin, count, queue);
+    else if (cls == 1)
+        hipLaunchKernelGGL(k_adj1d<9>, dim3(n_blocks), dim3(64), 0, st, A, begin, count, queue);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int adj1d_class_resident_blocks(int cls) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = cls == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj1d<1>, 64, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj1d<9>, 64, 0);
+    if (e != hipSuccess) return 0;
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+}  // namespace pbe

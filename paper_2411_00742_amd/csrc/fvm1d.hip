@@ -17,9 +17,9 @@ using namespace dev;
 template <int K, int SCHEME>
 __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
     const int lane = threadIdx.x;
-    const int N = a.ncell[s];
-    const int64_t base = a.off[s];
-    const double Lmax = a.Lmax[s];
+    const int N = uniform(a.ncell[s]);
+    const int64_t base = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
+    const double Lmax = uniform(a.Lmax[s]);
     const double dL = Lmax / N;
     const SimParams q = load_params(a.par + (size_t)s * PBE_NPAR);
     const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
@@ -34,14 +34,12 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
     const int i0 = lane * K - pad;   // cell index of slot 0
 
     double u[K];
-    const double* src = a.from_initial ? a.f0 + base : a.f + base;
-#pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = (i0 + k >= 0) ? src[max(i0 + k, 0)] : 0.0;
+    load_cells(u, (a.from_initial ? a.f0 : a.f) + base, i0, g.npad, 0.0);
 
     double C, t, mu3_old, out;
     int step, next, status;
     if (a.from_initial) {
-        C = a.C0[s];
+        C = uniform(a.C0[s]);
         t = 0.0;
         mu3_old = wave_sum(lane_moment3(u, g, dL)) * dL;
         out = 0.0;
@@ -59,7 +57,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
         asm volatile("" : "+v"(g.xb));
         if (step >= a.step_cap) { status |= PBE_SIM_STEPCAP; break; }
         const Rates r = rates_plain(p, q, C, t);
-        const double t_next = next < ns ? ts[min(next, ns - 1)] : p.t_end;
+        const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
         double dt;
         const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
         if (!(dt > 0.0) || !isfinite(dt)) {   // rates overflowed: stop this sim
@@ -72,12 +70,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
         if (a.ckpt_every > 0 && step % a.ckpt_every == 0) {
             const int c = step / a.ckpt_every;
             if (c < a.n_ckpt) {
-                int j0 = i0;
-                asm volatile("" : "+v"(j0));
-                double* dst = a.ck_f + base * a.n_ckpt + (int64_t)c * N + j0;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (j0 + k >= 0) dst[k] = u[k];
+                store_cells(u, a.ck_f + base * a.n_ckpt + (int64_t)c * N, i0, g.npad);
                 if (lane == 0) {
                     a.ck_C[(int64_t)s * a.n_ckpt + c] = C;
                     a.ck_t[(int64_t)s * a.n_ckpt + c] = t;
@@ -116,23 +109,14 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
                     a.C_s[o] = C;
                     a.samp_step[o] = step;
                 }
-                if (a.record_f) {
-                    int j0 = i0;
-                    asm volatile("" : "+v"(j0));
-                    double* dst = a.f_s + base * ns + (int64_t)next * N + j0;
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        if (j0 + k >= 0) dst[k] = u[k];
-                }
+                if (a.record_f) store_cells(u, a.f_s + base * ns + (int64_t)next * N, i0, g.npad);
                 ++next;
             }
         }
     }
 
     // save the running state
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (i0 + k >= 0) a.f[base + i0 + k] = u[k];
+    store_cells(u, a.f + base, i0, g.npad);
     const double out63 = lane_value(out, 63);
     if (!(t < p.t_end) || (status & PBE_SIM_NONFINITE)) {
         double m[4];
@@ -160,8 +144,8 @@ __global__ __launch_bounds__(64) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cl
         const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
         const int idx = __builtin_amdgcn_readfirstlane(ticket);
         if (idx >= cls_count) break;
-        const int s = a.order[cls_begin + idx];
-        const int K = (a.ncell[s] + 63) >> 6;
+        const int s = uniform(a.order[cls_begin + idx]);
+        const int K = uniform((a.ncell[s] + 63) >> 6);
         switch (K - KLO) {
             case 0: run_sim<KLO + 0, SCHEME>(a, s); break;
             case 1: run_sim<KLO + 1, SCHEME>(a, s); break;

@@ -82,10 +82,14 @@ struct SimParams {
     double kg, g, kb, b, gamma, Eg, Eb, T0, T1, tr;
 };
 
+// (each value is made explicitly wave-uniform: loaded through a vector load,
+// it would otherwise occupy a VGPR pair per parameter for the whole solve)
 __device__ __forceinline__ SimParams load_params(const double* P) {
     SimParams q;
-    q.kg = P[PBE_P_KG]; q.g = P[PBE_P_G]; q.kb = P[PBE_P_KB]; q.b = P[PBE_P_B]; q.gamma = P[PBE_P_GAMMA];
-    q.Eg = P[PBE_P_EG]; q.Eb = P[PBE_P_EB]; q.T0 = P[PBE_P_T0]; q.T1 = P[PBE_P_T1]; q.tr = P[PBE_P_TRAMP];
+    q.kg = uniform(P[PBE_P_KG]); q.g = uniform(P[PBE_P_G]); q.kb = uniform(P[PBE_P_KB]);
+    q.b = uniform(P[PBE_P_B]); q.gamma = uniform(P[PBE_P_GAMMA]);
+    q.Eg = uniform(P[PBE_P_EG]); q.Eb = uniform(P[PBE_P_EB]); q.T0 = uniform(P[PBE_P_T0]);
+    q.T1 = uniform(P[PBE_P_T1]); q.tr = uniform(P[PBE_P_TRAMP]);
     return q;
 }
 
@@ -118,6 +122,35 @@ __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& 
         r.B = q.kb * exp64(q.b * r.lnS) * r.arrB;
     }
     r.G0 = uniform(r.G0);
+    r.B = uniform(r.B);
+    r.S = uniform(r.S);
+    return r;
+}
+
+// Rates of the 2D model: growth along each axis (G1 with kg, g; G2 with kg2, g2)
+// and nucleation, all driven by the same supersaturation.
+struct Rates2 {
+    double G1, G2, B, S;
+};
+__device__ __forceinline__ Rates2 rates_2d(const Process& p, const SimParams& q, double kg2, double g2, double C,
+                                           double t) {
+    Rates2 r;
+    const double T = temperature(q, t);
+    r.S = C / solubility(p, T) - 1.0;
+    r.G1 = 0.0; r.G2 = 0.0; r.B = 0.0;
+    if (r.S > 0.0) {
+        const double lnS = log64(r.S);
+        double aG = 1.0, aB = 1.0;
+        if (p.law == PBE_LAW_ARRHENIUS) {
+            aG = exp64(-q.Eg / (T + 273.15));
+            aB = exp64(-q.Eb / (T + 273.15));
+        }
+        r.G1 = 1e6 * q.kg * exp64(q.g * lnS) * aG;
+        r.G2 = 1e6 * kg2 * exp64(g2 * lnS) * aG;
+        r.B = q.kb * exp64(q.b * lnS) * aB;
+    }
+    r.G1 = uniform(r.G1);
+    r.G2 = uniform(r.G2);
     r.B = uniform(r.B);
     r.S = uniform(r.S);
     return r;
@@ -184,19 +217,26 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
                                             face_weight(g, K - 1), c);
     const double HL = shift_from_left(Hlast, ghost);
     double Hprev = HL, um1 = uL;
+    double ui = u[0];
+    double xk = g.xb;   // cell index of slot k
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double up1 = (k + 1 < K) ? u[k + 1 < K ? k + 1 : 0] : uR;
-        const double H = (k == K - 1) ? Hlast : face_value<SCHEME>(um1, u[k], up1, face_weight(g, k), c);
-        const double v = u[k] + c * (Hprev - H);
-        double old = u[k];
-        u[k] = first ? v : wa * u0[k] + wb * v;
-        // Sliding-window order: the next face reads the old u[k] only after
-        // the new u[k] exists, so the scheduler cannot compute every face
-        // value up front (that keeps K extra doubles live and spills).
-        asm volatile("" : "+v"(old) : "v"(u[k]));
-        um1 = old;
+        const double w = fma(g.gdL, fmax(xk + 1.0, 0.0), 1.0);
+        const double H = (k == K - 1) ? Hlast : face_value<SCHEME>(um1, ui, up1, w, c);
+        const double v = ui + c * (Hprev - H);
+        const double nv = first ? v : wa * u0[k] + wb * v;
+        u[k] = nv;
         Hprev = H;
+        // Sliding-window order: every input of the next slot (its cell value,
+        // its left neighbour and its face coordinate) is made to depend on
+        // this slot's result, so the scheduler cannot compute the faces of all
+        // K slots up front (that keeps several arrays of K doubles live).
+        double next_um1 = ui, next_ui = up1, next_x = xk + 1.0;
+        asm volatile("" : "+v"(next_um1), "+v"(next_ui), "+v"(next_x) : "v"(nv));
+        um1 = next_um1;
+        ui = next_ui;
+        xk = next_x;
     }
     return Hlast;
 }
@@ -206,8 +246,7 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
 template <int K, int SCHEME>
 __device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, double c, double ghost) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (k < g.npad) u[k] = ghost;
+    for (int k = 0; k < K; ++k) u[k] = k < g.npad ? ghost : u[k];   // select, not a divergent branch
     if (SCHEME == PBE_SCHEME_LW_TVD) {
         double u0[K];
         return fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.0, 1.0, true);
@@ -219,6 +258,34 @@ __device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, do
     const double h1 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.75, 0.25, false);
     const double h2 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false);
     return h0 / 6.0 + h1 / 6.0 + (2.0 / 3.0) * h2;
+}
+
+// Load / store this lane's K cells of one simulation's packed array `row`
+// (cell 0 at row[0]).  Every per-cell device array carries a leading guard of
+// kCellGuard doubles, so row + (cell index of slot 0) stays inside the
+// allocation even for pad slots: loads are unconditional (pad slots then take
+// `pad_value` by a select), which keeps the K-slot array out of divergent
+// control flow (a per-slot guarded load makes the compiler copy the whole
+// array through every branch).  Stores of pad slots are masked off.
+template <int K>
+__device__ __forceinline__ void load_cells(double (&u)[K], const double* row, int i0, int npad, double pad_value) {
+    int j0 = i0;
+    asm volatile("" : "+v"(j0));
+    const double* lp = row + j0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double x = lp[k];
+        u[k] = k < npad ? pad_value : x;
+    }
+}
+template <int K>
+__device__ __forceinline__ void store_cells(const double (&u)[K], double* row, int i0, int npad) {
+    int j0 = i0;
+    asm volatile("" : "+v"(j0));
+    double* lp = row + j0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k >= npad) lp[k] = u[k];
 }
 
 // this lane's part of sum_i L_i^3 f_i (cell centres; pad slots weigh 0)

@@ -33,6 +33,13 @@ struct Alloc {
         ptrs.push_back(p);
         return static_cast<T*>(p);
     }
+    // per-cell arrays: kCellGuard leading doubles (zeroed) that kernels may read, never write
+    double* cells(size_t n) {
+        double* p = get<double>(n + kCellGuard);
+        if (!p) return nullptr;
+        if (hipMemset(p, 0, sizeof(double) * kCellGuard) != hipSuccess) ok = false;
+        return p + kCellGuard;
+    }
     void release() {
         for (void* p : ptrs) (void)hipFree(p);
         ptrs.clear();
@@ -68,17 +75,30 @@ struct pbe_handle {
     double* d_tape = nullptr;
     double* d_tapeC = nullptr;
     double* d_tapeT = nullptr;
+    double* d_gf = nullptr;          // staged cotangents (guarded per-cell array)
+    double* d_gmom = nullptr;
+    double* d_gC = nullptr;
+    int adj_blocks[kAdjClasses] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // 2D
+    bool two_d = false;
+    Fvm2dArgs a2{};
+    int row_begin[kRowClasses] = {}, row_count[kRowClasses] = {};
+    int64_t g2 = 0;                  // global step of the 2D solve (parity selects the buffer)
+    std::vector<int32_t> active_host;
     bool fresh = true;               // next pbe_step starts from the initial condition
     bool solved = false;             // a complete pbe_solve with checkpoints exists
 };
 
 namespace {
 
+int validate2d(const pbe_problem* p);
+
 int validate(const pbe_problem* p) {
     if (!p) return PBE_EINVAL;
-    if (p->ndim != 1) return p->ndim == 2 ? PBE_EUNSUPPORTED : PBE_EINVAL;
+    if (p->ndim == 2) return validate2d(p);
+    if (p->ndim != 1) return PBE_EINVAL;
     if (p->n_sims < 1 || !p->n_cells || !p->L_max || !p->f0 || !p->C0 || !p->par || !p->t_samples) return PBE_EINVAL;
     if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return p->law == PBE_LAW_MLP ? PBE_EUNSUPPORTED : PBE_EINVAL;
     if (p->scheme != PBE_SCHEME_SSPRK3 && p->scheme != PBE_SCHEME_LW_TVD) return PBE_EINVAL;
@@ -93,6 +113,12 @@ int validate(const pbe_problem* p) {
         if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
     }
     if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
+    if (p->ckpt_every > 0) {
+        // the adjoint covers the SSP-RK3 scheme on grids up to 64*16 cells
+        if (p->scheme != PBE_SCHEME_SSPRK3) return PBE_EUNSUPPORTED;
+        for (int s = 0; s < p->n_sims; ++s)
+            if (p->n_cells[s] > kWave * 8 * kAdjClasses) return PBE_EUNSUPPORTED;
+    }
     if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F)) return PBE_EINVAL;
     int64_t total = 0;
     for (int s = 0; s < p->n_sims; ++s) {
@@ -109,6 +135,54 @@ int validate(const pbe_problem* p) {
         if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0)) return PBE_EINVAL;
         if (!(solubility(p, q[PBE_P_T0]) > 0.0) || !(solubility(p, q[PBE_P_T1]) > 0.0)) return PBE_EINVAL;
         total += n;
+    }
+    for (int64_t i = 0; i < total; ++i)
+        if (!is_finite(p->f0[i]) || p->f0[i] < 0.0) return PBE_EINVAL;
+    return PBE_OK;
+}
+
+int validate_common(const pbe_problem* p) {
+    if (p->n_sims < 1 || !p->n_cells || !p->L_max || !p->f0 || !p->C0 || !p->par || !p->t_samples) return PBE_EINVAL;
+    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return p->law == PBE_LAW_MLP ? PBE_EUNSUPPORTED : PBE_EINVAL;
+    if (p->scheme != PBE_SCHEME_SSPRK3 && p->scheme != PBE_SCHEME_LW_TVD) return PBE_EINVAL;
+    if (p->sol_law != PBE_SOL_LINEAR && p->sol_law != PBE_SOL_EXP) return PBE_EINVAL;
+    if (!is_finite(p->cs0) || !is_finite(p->cs1) || !is_finite(p->alpha) || p->alpha < 0.0) return PBE_EINVAL;
+    if (!(p->cfl > 0.0 && p->cfl <= 1.0) || !(p->dt_max > 0.0) || !is_finite(p->dt_max)) return PBE_EINVAL;
+    if (!(p->t_end > 0.0) || !is_finite(p->t_end)) return PBE_EINVAL;
+    if (p->n_samples < 1) return PBE_EINVAL;
+    for (int q = 0; q < p->n_samples; ++q) {
+        const double tq = p->t_samples[q];
+        if (!is_finite(tq) || !(tq > 0.0) || tq > p->t_end) return PBE_EINVAL;
+        if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
+    }
+    if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
+    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F)) return PBE_EINVAL;
+    return PBE_OK;
+}
+
+int validate2d(const pbe_problem* p) {
+    int rc = validate_common(p);
+    if (rc != PBE_OK) return rc;
+    // the split solver runs SSP-RK3 sweeps, forward only, outputs are moments and final states
+    if (p->scheme != PBE_SCHEME_SSPRK3 || p->ckpt_every != 0 || (p->flags & PBE_FLAG_RECORD_F))
+        return PBE_EUNSUPPORTED;
+    int64_t total = 0;
+    for (int s = 0; s < p->n_sims; ++s) {
+        const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
+        if (n1 < 4 || n1 > kWave * kMaxCellsPerLane || n2 < 4 || n2 > 8192) return PBE_EINVAL;
+        if (!is_finite(p->L_max[2 * s]) || !(p->L_max[2 * s] > 0.0) || !is_finite(p->L_max[2 * s + 1]) ||
+            !(p->L_max[2 * s + 1] > 0.0))
+            return PBE_EINVAL;
+        if (!is_finite(p->C0[s]) || !(p->C0[s] > 0.0)) return PBE_EINVAL;
+        const double* q = p->par + (size_t)s * PBE_NPAR;
+        for (int k = 0; k < PBE_NPAR; ++k)
+            if (!is_finite(q[k])) return PBE_EINVAL;
+        if (q[PBE_P_KG] < 0.0 || q[PBE_P_KG2] < 0.0 || q[PBE_P_KB] < 0.0 || !(q[PBE_P_G] > 0.0) ||
+            !(q[PBE_P_G2] > 0.0) || !(q[PBE_P_B] > 0.0) || q[PBE_P_TRAMP] < 0.0)
+            return PBE_EINVAL;
+        if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0)) return PBE_EINVAL;
+        if (!(solubility(p, q[PBE_P_T0]) > 0.0) || !(solubility(p, q[PBE_P_T1]) > 0.0)) return PBE_EINVAL;
+        total += (int64_t)n1 * n2;
     }
     for (int64_t i = 0; i < total; ++i)
         if (!is_finite(p->f0[i]) || p->f0[i] < 0.0) return PBE_EINVAL;
@@ -222,6 +296,228 @@ int write_outputs(pbe_handle* h, double* f_out, double* mom_out, double* C_out, 
     return rc;
 }
 
+// ----------------------------------------------------------------- 2D
+constexpr int k2dSeg = 128;         // rows per L2-sweep block
+constexpr int k2dStepsPerGraph = 50;  // global steps captured per graph launch (even)
+
+double step_bound2d(const pbe_problem* p, int s) {
+    const double* q = p->par + (size_t)s * PBE_NPAR;
+    const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
+    const double d1 = p->L_max[2 * s] / n1, d2 = p->L_max[2 * s + 1] / n2;
+    double mu12 = 0.0;
+    const double* f = p->f0;
+    int64_t o = 0;
+    for (int k = 0; k < s; ++k) o += (int64_t)p->n_cells[2 * k] * p->n_cells[2 * k + 1];
+    for (int j = 0; j < n2; ++j)
+        for (int i = 0; i < n1; ++i) {
+            const double L1 = (i + 0.5) * d1, L2 = (j + 0.5) * d2;
+            mu12 += L1 * L2 * L2 * f[o + (int64_t)j * n1 + i] * d1 * d2;
+        }
+    const double csat_min = std::min(solubility(p, q[PBE_P_T0]), solubility(p, q[PBE_P_T1]));
+    const double Smax = std::max(0.0, (p->C0[s] + p->alpha * mu12) / csat_min - 1.0);
+    const double G1 = 1e6 * q[PBE_P_KG] * std::pow(Smax, q[PBE_P_G]);
+    const double G2 = 1e6 * q[PBE_P_KG2] * std::pow(Smax, q[PBE_P_G2]);
+    double lim = std::numeric_limits<double>::infinity();
+    if (G1 > 0.0) lim = std::min(lim, d1 / G1);
+    if (G2 > 0.0) lim = std::min(lim, d2 / G2);
+    const double dt_min = std::min(p->dt_max, p->cfl * lim);
+    return p->t_end / dt_min + p->n_samples + 2.0;
+}
+
+int create2d(pbe_handle* h, const pbe_problem* p) {
+    h->two_d = true;
+    const int S = h->S, ns = h->ns;
+    h->off.assign(S + 1, 0);
+    for (int s = 0; s < S; ++s) h->off[s + 1] = h->off[s] + (int64_t)p->n_cells[2 * s] * p->n_cells[2 * s + 1];
+    h->total = h->off[S];
+    double cap = 0.0;
+    for (int s = 0; s < S; ++s) cap = std::max(cap, step_bound2d(p, s));
+    const int step_cap = p->max_steps > 0 ? p->max_steps : (int)std::min(1.0e9, std::ceil(cap * 1.05) + 8.0);
+
+    // work lists: rows grouped by class of cells per lane; column blocks sim by sim
+    std::vector<int32_t> row_sim, row_j;
+    for (int c = 0; c < kRowClasses; ++c) {
+        h->row_begin[c] = (int)row_sim.size();
+        for (int s = 0; s < S; ++s) {
+            const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
+            if (fvm1d_class_of(n1) != c) continue;
+            for (int j = 0; j < n2; ++j) {
+                row_sim.push_back(s);
+                row_j.push_back(j);
+            }
+        }
+        h->row_count[c] = (int)row_sim.size() - h->row_begin[c];
+    }
+    std::vector<int32_t> cb_sim, cb_col0, cb_row0, cb_first(S + 1, 0);
+    for (int s = 0; s < S; ++s) {
+        cb_first[s] = (int)cb_sim.size();
+        const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
+        for (int c0 = 0; c0 < n1; c0 += kWave)
+            for (int r0 = 0; r0 < n2; r0 += k2dSeg) {
+                cb_sim.push_back(s);
+                cb_col0.push_back(c0);
+                cb_row0.push_back(r0);
+            }
+    }
+    cb_first[S] = (int)cb_sim.size();
+    std::vector<int32_t> n1v(S), n2v(S);
+    std::vector<double> L1v(S), L2v(S);
+    for (int s = 0; s < S; ++s) {
+        n1v[s] = p->n_cells[2 * s];
+        n2v[s] = p->n_cells[2 * s + 1];
+        L1v[s] = p->L_max[2 * s];
+        L2v[s] = p->L_max[2 * s + 1];
+    }
+
+    Alloc& m = h->mem;
+    Fvm2dArgs& a = h->a2;
+    a.n_sims = S; a.n_samples = ns; a.law = p->law; a.sol_law = p->sol_law;
+    a.cs0 = p->cs0; a.cs1 = p->cs1; a.alpha = p->alpha; a.cfl = p->cfl; a.dt_max = p->dt_max; a.t_end = p->t_end;
+    double* d_ts = m.get<double>(ns);
+    int64_t* d_off = m.get<int64_t>(S + 1);
+    int32_t* d_n1 = m.get<int32_t>(S);
+    int32_t* d_n2 = m.get<int32_t>(S);
+    double* d_L1 = m.get<double>(S);
+    double* d_L2 = m.get<double>(S);
+    double* d_par = m.get<double>((size_t)S * PBE_NPAR);
+    double* d_C0 = m.get<double>(S);
+    double* d_f0 = m.cells(h->total);
+    a.buf[0] = m.cells(h->total);
+    a.buf[1] = m.cells(h->total);
+    a.C = m.get<double>(S); a.t = m.get<double>(S); a.mu12 = m.get<double>(S);
+    a.step = m.get<int32_t>(S); a.next = m.get<int32_t>(S); a.status = m.get<int32_t>(S);
+    a.active = m.get<int32_t>(S); a.n_active = m.get<int32_t>(1);
+    a.c1 = m.get<double>(S); a.c2 = m.get<double>(S); a.gh1 = m.get<double>(S); a.gh2 = m.get<double>(S);
+    a.dt = m.get<double>(S); a.hit = m.get<int32_t>(S);
+    int32_t* d_row_sim = m.get<int32_t>(row_sim.size());
+    int32_t* d_row_j = m.get<int32_t>(row_j.size());
+    int32_t* d_cb_sim = m.get<int32_t>(cb_sim.size());
+    int32_t* d_cb_col0 = m.get<int32_t>(cb_sim.size());
+    int32_t* d_cb_row0 = m.get<int32_t>(cb_sim.size());
+    int32_t* d_cb_first = m.get<int32_t>(S + 1);
+    a.part = m.get<double>(cb_sim.size() * 4);
+    a.mom_s = m.get<double>((size_t)S * ns * 4);
+    a.C_s = m.get<double>((size_t)S * ns);
+    a.samp_step = m.get<int32_t>((size_t)S * ns);
+    if (!m.ok) return PBE_ENOMEM;
+    a.t_samples = d_ts; a.off = d_off; a.n1 = d_n1; a.n2 = d_n2; a.L1 = d_L1; a.L2 = d_L2; a.par = d_par;
+    a.C0 = d_C0; a.f0 = d_f0;
+    a.row_sim = d_row_sim; a.row_j = d_row_j;
+    a.cb_sim = d_cb_sim; a.cb_col0 = d_cb_col0; a.cb_row0 = d_cb_row0; a.cb_first = d_cb_first;
+    a.n_cb = (int)cb_sim.size();
+    a.seg = k2dSeg;
+    a.step_cap = step_cap;
+    // the 1D argument block shares the sample buffers so pbe_fetch/pbe_solve copy outputs the same way
+    h->a.mom_s = a.mom_s;
+    h->a.C_s = a.C_s;
+    h->a.step = a.step;
+    h->a.status = a.status;
+    h->a.record_f = 0;
+    if (hipMemcpy(d_ts, p->t_samples, sizeof(double) * ns, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_off, h->off.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_n1, n1v.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_n2, n2v.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_L1, L1v.data(), sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_L2, L2v.data(), sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_par, p->par, sizeof(double) * S * PBE_NPAR, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_C0, p->C0, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_row_sim, row_sim.data(), sizeof(int32_t) * row_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_row_j, row_j.data(), sizeof(int32_t) * row_j.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_cb_sim, cb_sim.data(), sizeof(int32_t) * cb_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_cb_col0, cb_col0.data(), sizeof(int32_t) * cb_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_cb_row0, cb_row0.data(), sizeof(int32_t) * cb_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_cb_first, cb_first.data(), sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return PBE_EDEVICE;
+    h->active_host.assign(S, 0);
+    return PBE_OK;
+}
+
+// one global step of every active 2D sim
+int step2d_once(pbe_handle* h) {
+    const int parity = (int)(h->g2 & 1);
+    for (int c = 0; c < kRowClasses; ++c)
+        HIP_OK(launch_rows2d(c, h->a2, parity, h->row_begin[c], h->row_count[c], h->stream));
+    HIP_OK(launch_cols2d(h->a2, parity, h->stream));
+    HIP_OK(launch_final2d(h->a2, 0, h->stream));
+    ++h->g2;
+    return PBE_OK;
+}
+
+int start2d(pbe_handle* h) {
+    Fvm2dArgs& a = h->a2;
+    HIP_OK(hipMemcpyAsync(a.buf[0], a.f0, sizeof(double) * h->total, hipMemcpyDeviceToDevice, h->stream));
+    int rc = fill(a.mom_s, (int64_t)h->S * h->ns * 4, h->stream);
+    if (rc == PBE_OK) rc = fill(a.C_s, (int64_t)h->S * h->ns, h->stream);
+    if (rc != PBE_OK) return rc;
+    HIP_OK(launch_final2d(a, 1, h->stream));
+    h->g2 = 0;
+    return PBE_OK;
+}
+
+int count_active2d(pbe_handle* h, int* n) {
+    HIP_OK(hipMemcpyAsync(h->active_host.data(), h->a2.active, sizeof(int32_t) * h->S, hipMemcpyDeviceToHost,
+                          h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    int k = 0;
+    for (int v : h->active_host) k += v;
+    *n = k;
+    return PBE_OK;
+}
+
+int solve2d(pbe_handle* h) {
+    int rc = start2d(h);
+    if (rc != PBE_OK) return rc;
+    if (!h->graph_exec) {
+        // k2dStepsPerGraph global steps (an even number, so the buffer parity of
+        // the captured launches matches every replay)
+        if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PBE_EDEVICE;
+        const int64_t g_save = h->g2;
+        for (int k = 0; k < k2dStepsPerGraph && rc == PBE_OK; ++k) rc = step2d_once(h);
+        h->g2 = g_save;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (rc != PBE_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != PBE_OK ? rc : PBE_EDEVICE;
+        }
+        if (hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            h->graph_exec = nullptr;
+            return PBE_EDEVICE;
+        }
+        h->graph = g;
+    }
+    for (;;) {
+        HIP_OK(hipGraphLaunch(h->graph_exec, h->stream));
+        h->g2 += k2dStepsPerGraph;
+        int n = 0;
+        rc = count_active2d(h, &n);
+        if (rc != PBE_OK) return rc;
+        if (n == 0) break;
+        if (h->g2 > (int64_t)h->a2.step_cap + k2dStepsPerGraph) return PBE_EDEVICE;
+    }
+    return PBE_OK;
+}
+
+int write_outputs2d(pbe_handle* h, double* f_out, double* mom_out, double* C_out, int32_t* steps_out,
+                    int32_t* status_out) {
+    const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
+    if (f_out) {
+        if (dev) {
+            HIP_OK(launch_out2d(h->a2, f_out, h->stream));
+        } else {
+            // stage the final state through buf[g % 2] of the other parity? use a scratch copy
+            double* tmp = nullptr;
+            if (hipMallocAsync((void**)&tmp, sizeof(double) * h->total, h->stream) != hipSuccess) return PBE_ENOMEM;
+            HIP_OK(launch_out2d(h->a2, tmp, h->stream));
+            HIP_OK(hipMemcpyAsync(f_out, tmp, sizeof(double) * h->total, hipMemcpyDeviceToHost, h->stream));
+            HIP_OK(hipFreeAsync(tmp, h->stream));
+        }
+    }
+    return write_outputs(h, nullptr, mom_out, C_out, steps_out, status_out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -252,6 +548,17 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     h->user = static_cast<hipStream_t>(hip_stream);
     h->S = p->n_sims;
     h->ns = p->n_samples;
+    if (p->ndim == 2) {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess)
+            return fail(h, PBE_EDEVICE);
+        const int rc = create2d(h, p);
+        if (rc != PBE_OK) return fail(h, rc);
+        *out = h;
+        return PBE_OK;
+    }
     h->ncell.assign(p->n_cells, p->n_cells + h->S);
     h->off.assign(h->S + 1, 0);
     for (int s = 0; s < h->S; ++s) h->off[s + 1] = h->off[s] + h->ncell[s];
@@ -300,22 +607,28 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     double* d_Lmax = m.get<double>(S);
     double* d_par = m.get<double>((size_t)S * PBE_NPAR);
     double* d_C0 = m.get<double>(S);
-    double* d_f0 = m.get<double>(h->total);
-    a.f = m.get<double>(h->total);
+    double* d_f0 = m.cells(h->total);
+    a.f = m.cells(h->total);
     a.C = m.get<double>(S); a.t = m.get<double>(S); a.mu3 = m.get<double>(S); a.outflow = m.get<double>(S);
     a.step = m.get<int32_t>(S); a.next = m.get<int32_t>(S); a.status = m.get<int32_t>(S);
     a.mom_s = m.get<double>((size_t)S * ns * 4);
     a.C_s = m.get<double>((size_t)S * ns);
     a.samp_step = m.get<int32_t>((size_t)S * ns);
-    a.f_s = a.record_f ? m.get<double>((size_t)h->total * ns) : nullptr;
+    a.f_s = a.record_f ? m.cells((size_t)h->total * ns) : nullptr;
     a.ckpt_every = p->ckpt_every;
     a.n_ckpt = 0;
     if (p->ckpt_every > 0) {
         a.n_ckpt = step_cap / p->ckpt_every + 2;
-        a.ck_f = m.get<double>((size_t)h->total * a.n_ckpt);
+        a.ck_f = m.cells((size_t)h->total * a.n_ckpt);
         a.ck_C = m.get<double>((size_t)S * a.n_ckpt);
         a.ck_t = m.get<double>((size_t)S * a.n_ckpt);
         h->d_gpar = m.get<double>((size_t)S * PBE_NGRAD);
+        h->d_tape = m.cells((size_t)h->total * p->ckpt_every);
+        h->d_tapeC = m.get<double>((size_t)S * p->ckpt_every);
+        h->d_tapeT = m.get<double>((size_t)S * p->ckpt_every);
+        h->d_gf = m.cells((size_t)h->total * (a.record_f ? ns : 1));
+        h->d_gmom = m.get<double>((size_t)S * ns * 4);
+        h->d_gC = m.get<double>((size_t)S * ns);
     }
     if (!m.ok) return fail(h, PBE_ENOMEM);
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
@@ -344,6 +657,12 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
             return fail(h, PBE_EDEVICE);
         if (hipEventCreateWithFlags(&h->ev_join[c], hipEventDisableTiming) != hipSuccess) return fail(h, PBE_EDEVICE);
     }
+    if (p->ckpt_every > 0)
+        for (int c = 0; c < kAdjClasses; ++c) {
+            const int resident = adj1d_class_resident_blocks(c);
+            if (resident <= 0) return fail(h, PBE_EDEVICE);
+            h->adj_blocks[c] = std::max(1, std::min(h->cls_count[c], resident));
+        }
     if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess ||
         hipEventCreate(&h->ev_g0) != hipSuccess || hipEventCreate(&h->ev_g1) != hipSuccess)
@@ -361,6 +680,20 @@ int pbe_reset(pbe_handle* h) {
 
 int pbe_step(pbe_handle* h, int32_t n_steps, int32_t* n_active_out) {
     if (!h || n_steps < 0) return PBE_EINVAL;
+    if (h->two_d) {
+        int rc = enter(h);
+        if (rc == PBE_OK && h->fresh) rc = start2d(h);
+        for (int k = 0; k < n_steps && rc == PBE_OK; ++k) rc = step2d_once(h);
+        if (rc == PBE_OK) rc = leave(h);
+        if (rc != PBE_OK) return rc;
+        h->fresh = false;
+        if (n_active_out) {
+            int n = 0;
+            rc = count_active2d(h, &n);
+            *n_active_out = n;
+        }
+        return rc;
+    }
     int rc = enter(h);
     if (rc == PBE_OK && h->fresh) rc = clear_samples(h);
     if (rc == PBE_OK) rc = launch_classes(h, h->fresh ? 1 : 0, n_steps);
@@ -385,6 +718,16 @@ int pbe_step(pbe_handle* h, int32_t n_steps, int32_t* n_active_out) {
 int pbe_solve(pbe_handle* h, double* f_out, double* mom_out, double* C_out, int32_t* steps_out,
               int32_t* status_out) {
     if (!h) return PBE_EINVAL;
+    if (h->two_d) {
+        if (enter(h) != PBE_OK) return PBE_EDEVICE;
+        HIP_OK(hipEventRecord(h->ev_t0, h->stream));
+        const int rc = solve2d(h);
+        if (rc != PBE_OK) return rc;
+        HIP_OK(hipEventRecord(h->ev_t1, h->stream));
+        h->timed_solve = true;
+        h->fresh = false;
+        return write_outputs2d(h, f_out, mom_out, C_out, steps_out, status_out);
+    }
     if (!h->graph_exec) {
         // one graph: clear samples, reset queues, fork the class kernels, join
         if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PBE_EDEVICE;
@@ -418,6 +761,7 @@ int pbe_fetch(pbe_handle* h, double* f_out, double* mom_out, double* C_out, int3
     if (!h) return PBE_EINVAL;
     if (h->fresh) return PBE_ESTATE;
     if (enter(h) != PBE_OK) return PBE_EDEVICE;
+    if (h->two_d) return write_outputs2d(h, f_out, mom_out, C_out, steps_out, status_out);
     return write_outputs(h, f_out, mom_out, C_out, steps_out, status_out);
 }
 
@@ -430,10 +774,12 @@ int pbe_set_par(pbe_handle* h, const double* par) {
         if (q[PBE_P_KG] < 0.0 || q[PBE_P_KB] < 0.0 || !(q[PBE_P_G] > 0.0) || !(q[PBE_P_B] > 0.0) ||
             q[PBE_P_GAMMA] < 0.0 || q[PBE_P_TRAMP] < 0.0)
             return PBE_EINVAL;
+        if (h->two_d && (q[PBE_P_KG2] < 0.0 || !(q[PBE_P_G2] > 0.0))) return PBE_EINVAL;
     }
     // the previous launches may still read the parameters: wait for them first
     HIP_OK(hipStreamSynchronize(h->stream));
-    HIP_OK(hipMemcpy(const_cast<double*>(h->a.par), par, sizeof(double) * h->S * PBE_NPAR, hipMemcpyHostToDevice));
+    const double* dpar = h->two_d ? h->a2.par : h->a.par;
+    HIP_OK(hipMemcpy(const_cast<double*>(dpar), par, sizeof(double) * h->S * PBE_NPAR, hipMemcpyHostToDevice));
     h->fresh = true;
     h->solved = false;
     return PBE_OK;
@@ -441,10 +787,54 @@ int pbe_set_par(pbe_handle* h, const double* par) {
 
 int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
              float* gmlp_out) {
-    (void)gf; (void)gmom; (void)gC; (void)gpar_out; (void)gmlp_out;
+    (void)gmlp_out;
     if (!h) return PBE_EINVAL;
+    if (h->two_d) return PBE_EUNSUPPORTED;
     if (h->p.ckpt_every <= 0 || !h->solved) return PBE_ESTATE;
-    return PBE_EUNSUPPORTED;
+    const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const size_t nf = (size_t)h->total * (h->a.record_f ? h->ns : 1);
+    const size_t nm = (size_t)h->S * h->ns * 4, nc = (size_t)h->S * h->ns;
+    if (enter(h) != PBE_OK) return PBE_EDEVICE;
+    // stage the cotangents (the per-cell one into a guarded array the kernel may over-read)
+    Adj1dArgs A{};
+    A.fw = h->a;
+    A.gf_is_final = h->a.record_f ? 0 : 1;
+    if (gf) {
+        HIP_OK(hipMemcpyAsync(h->d_gf, gf, sizeof(double) * nf, kind, h->stream));
+        A.gf = h->d_gf;
+    }
+    if (gmom) {
+        HIP_OK(hipMemcpyAsync(h->d_gmom, gmom, sizeof(double) * nm, kind, h->stream));
+        A.gmom = h->d_gmom;
+    }
+    if (gC) {
+        HIP_OK(hipMemcpyAsync(h->d_gC, gC, sizeof(double) * nc, kind, h->stream));
+        A.gC = h->d_gC;
+    }
+    A.gpar = h->d_gpar;
+    A.tape = h->d_tape;
+    A.tape_C = h->d_tapeC;
+    A.tape_t = h->d_tapeT;
+    HIP_OK(hipEventRecord(h->ev_g0, h->stream));
+    HIP_OK(launch_reset_counter(h->d_queue, kFvmClasses, h->stream));
+    HIP_OK(hipEventRecord(h->ev_fork, h->stream));
+    for (int c = 0; c < kAdjClasses; ++c) {
+        if (h->cls_count[c] == 0) continue;
+        hipStream_t st = c == 0 ? h->stream : h->side[c];
+        if (c != 0) HIP_OK(hipStreamWaitEvent(st, h->ev_fork, 0));
+        HIP_OK(launch_adj1d_class(c, A, h->adj_blocks[c], h->cls_begin[c], h->cls_count[c], h->d_queue + c, st));
+        if (c != 0) {
+            HIP_OK(hipEventRecord(h->ev_join[c], st));
+            HIP_OK(hipStreamWaitEvent(h->stream, h->ev_join[c], 0));
+        }
+    }
+    HIP_OK(hipEventRecord(h->ev_g1, h->stream));
+    h->timed_grad = true;
+    int rc = copy_out(h, gpar_out, h->d_gpar, sizeof(double) * (size_t)h->S * PBE_NGRAD);
+    if (rc == PBE_OK) rc = leave(h);
+    if (rc == PBE_OK && !dev) HIP_OK(hipStreamSynchronize(h->stream));
+    return rc;
 }
 
 int pbe_last_kernel_ms(pbe_handle* h, float* solve_ms, float* grad_ms) {

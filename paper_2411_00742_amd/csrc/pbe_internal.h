@@ -11,6 +11,9 @@ namespace pbe {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxCellsPerLane = 32;  // 1D grids up to 64*32 = 2048 cells per wavefront
+// leading guard (in doubles) of every per-cell device array: a lane's slot-0
+// pointer may sit up to 64*K - N < 2048 cells before a simulation's first cell
+constexpr int kCellGuard = 2048;
 
 // Everything the 1D forward kernel reads or writes.  Device pointers only.
 struct Fvm1dArgs {
@@ -65,6 +68,54 @@ struct Adj1dArgs {
     int32_t pad_;
 };
 
+// 2D Godunov-split solver: per global step an L1 row sweep (in place), an L2
+// column march (double buffered) with moment partials, and a per-sim finalize.
+struct Fvm2dArgs {
+    int32_t n_sims, n_samples;
+    int32_t law, sol_law;
+    double cs0, cs1, alpha, cfl, dt_max, t_end;
+    const double* t_samples;
+    const int64_t* off;        // [S+1] cell offsets (sim s stored [n2][n1])
+    const int32_t* n1;         // [S]
+    const int32_t* n2;         // [S]
+    const double* L1;          // [S]
+    const double* L2;          // [S]
+    const double* par;         // [S*PBE_NPAR]
+    const double* C0;          // [S]
+    const double* f0;          // [sum n1*n2]
+    double* buf[2];            // state buffers: before global step g the state is in buf[g % 2]
+    // per-sim scalars
+    double* C;                 // [S]
+    double* t;                 // [S]
+    double* mu12;              // [S] volume moment of the current state
+    int32_t* step;             // [S]
+    int32_t* next;             // [S]
+    int32_t* status;           // [S]
+    int32_t* active;           // [S] 1 while the sim still steps
+    int32_t* n_active;         // [1] number of active sims after the last finalize
+    double* c1;                // [S] Courant factors dt*G/dL of the current step
+    double* c2;
+    double* gh1;               // [S] inflow ghost of row 0 (L1 sweep) and column 0 (L2 sweep)
+    double* gh2;
+    double* dt;                // [S]
+    int32_t* hit;              // [S] step lands on the next sample time
+    // L1 sweep: row tasks grouped by class of cells per lane
+    const int32_t* row_sim;    // [n_rows]
+    const int32_t* row_j;      // [n_rows]
+    // L2 sweep: column blocks (64 columns x seg rows)
+    const int32_t* cb_sim;     // [n_cb]
+    const int32_t* cb_col0;
+    const int32_t* cb_row0;
+    const int32_t* cb_first;   // [S+1] first column block of each sim
+    int32_t n_cb, seg;
+    double* part;              // [n_cb][4] partial moments of the swept state
+    double* mom_s;             // [S][n_samples][4]: mu_00, mu_10, mu_01, mu_12
+    double* C_s;               // [S][n_samples]
+    int32_t* samp_step;        // [S][n_samples]
+    int32_t step_cap;
+    int32_t pad_;
+};
+
 // Launchers (defined in the .hip files).  Return hipSuccess or the launch error.
 constexpr int kFvmClasses = 4;   // kernel classes by cells per lane: 1-8, 9-16, 17-24, 25-32
 inline int fvm1d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
@@ -72,8 +123,15 @@ hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int beg
                               hipStream_t st);
 hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st);
 int fvm1d_class_resident_blocks(int cls);
-hipError_t launch_adj1d(const Adj1dArgs& a, int n_blocks, hipStream_t st);
-int adj1d_max_resident_blocks();
+constexpr int kAdjClasses = 2;   // adjoint classes: cells per lane 1-8, 9-16 (grids up to 1024 cells)
+hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
+                              hipStream_t st);
+int adj1d_class_resident_blocks(int cls);
+constexpr int kRowClasses = 4;   // row sweep classes by cells per lane (rows up to 2048 cells)
+hipError_t launch_rows2d(int cls, const Fvm2dArgs& a, int parity, int begin, int count, hipStream_t st);
+hipError_t launch_cols2d(const Fvm2dArgs& a, int parity, hipStream_t st);
+hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st);
+hipError_t launch_out2d(const Fvm2dArgs& a, double* f_out, hipStream_t st);
 
 }  // namespace pbe
 

@@ -22,3 +22,10 @@ def oracle():
     from oracle import ref
     ref.lib()
     return ref
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch

@@ -12,13 +12,6 @@ from paper_2411_00742_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def torch_cuda():
-    import torch
-    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
-    return torch
-
-
 def run_gpu(prob, record_f=False, **kw):
     import paper_2411_00742_amd as pbe
     s = pbe.Solver(prob, record_f=record_f, **kw)
