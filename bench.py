@@ -76,6 +76,63 @@ def cpu_baseline(prob, stride: int, threads: int):
                        f"{cells:.3e} cell-updates in {el:.1f} s")
 
 
+def gradient_leg(steps: int):
+    """Per-simulation gradients per second: forward solve with checkpoints every 64 steps plus the
+    discrete adjoint, on 1024 sims x 1000 cells with 20 recorded samples (the estimation workload)."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    from paper_2411_00742_amd import workloads as W
+    prob = W.estimation()[0]
+    solver = pbe.Solver(prob, ckpt_every=64, record_f=True)
+    out = solver.solve()
+    rng = np.random.default_rng(1)
+    gf = torch.tensor(rng.normal(size=out["f"].numel()), device=out["f"].device)
+    gmom = torch.tensor(rng.normal(size=tuple(out["mom"].shape)), device=out["f"].device)
+    gC = torch.tensor(rng.normal(size=tuple(out["C"].shape)), device=out["f"].device)
+    g = solver.grad(gf, gmom, gC)
+    torch.cuda.synchronize()
+    steps_per_sim = out["steps"].cpu().numpy().astype(np.int64)
+    fw_ms, ad_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.solve(out)
+        g = solver.grad(gf, gmom, gC)
+        a, b = solver.last_kernel_ms()
+        fw_ms.append(a)
+        ad_ms.append(b)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    finite = bool(torch.isfinite(g).all().item())
+    cell_steps = int((steps_per_sim * prob.n_cells.astype(np.int64)).sum())
+    solver.close()
+    return dict(value=prob.n_sims / el, unit="per-sim gradients/s (5 params each, forward + adjoint)",
+                n_sims=prob.n_sims, cells=int(prob.n_cells[0]), ckpt_every=64, ms_per_gradient_batch=1e3 * el,
+                forward_span_ms=float(np.mean(fw_ms)), adjoint_span_ms=float(np.mean(ad_ms)),
+                cell_steps_per_solve=cell_steps, finite=finite)
+
+
+def fvm2d_leg(steps: int):
+    """2D length x width workload: 64 sims on n x n grids, n ~ U{256..1024}, Lie-split SSP-RK3."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    from paper_2411_00742_amd import workloads as W
+    prob = W.shape_2d()
+    solver = pbe.Solver(prob)
+    out = solver.solve()
+    torch.cuda.synchronize()
+    st = out["steps"].cpu().numpy().astype(np.int64)
+    cells = prob.n_cells.reshape(-1, 2).astype(np.int64).prod(axis=1)
+    cu = int((st * cells).sum())
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.solve(out)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    solver.close()
+    return dict(value=cu / el, unit="cell-updates/s", n_sims=prob.n_sims, cells=int(cells.sum()),
+                cell_updates_per_solve=cu, ms_per_solve=1e3 * el)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +140,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--plain-sims", type=int, default=32)
+    ap.add_argument("--no-grad", action="store_true", help="skip the adjoint-gradient leg")
+    ap.add_argument("--grad-steps", type=int, default=3)
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D leg")
+    ap.add_argument("--steps-2d", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the batched solver shards "
@@ -159,6 +220,12 @@ def main():
         "roofline": roofline,
         "kernel_ms": avg_kernel_ms,
     }
+    if not args.no_grad:
+        result["gradient"] = gradient_leg(args.grad_steps)
+        log(f"[bench] gradient leg: {result['gradient']}")
+    if not args.no_2d:
+        result["fvm2d"] = fvm2d_leg(args.steps_2d)
+        log(f"[bench] 2D leg: {result['fvm2d']}")
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(prob, 16, threads)

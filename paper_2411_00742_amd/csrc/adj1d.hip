@@ -57,9 +57,11 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
         const double s = same ? a + b : 1.0;
         const double r = 1.0 / s;
         const double psi = same ? (p + p) * r : 0.0;
-        const double r2 = 2.0 * r * r;
-        const double psia = same ? b * b * r2 : 0.0;
-        const double psib = same ? a * a * r2 : 0.0;
+        // d psi/da = 2 (b/(a+b))^2, d psi/db = 2 (a/(a+b))^2: both ratios lie in (0, 1]
+        // when ab > 0, so neither factor over- or underflows in the far tails of f
+        const double br = b * r, ar = a * r;
+        const double psia = same ? 2.0 * br * br : 0.0;
+        const double psib = same ? 2.0 * ar * ar : 0.0;
         const double Lf = fmax(g.xb + (double)(k + 1), 0.0) * dL;
         const double w = fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0);
         const double face = uk + 0.5 * psi;

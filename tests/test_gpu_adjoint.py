@@ -93,6 +93,8 @@ def test_adjoint_matches_central_differences_of_gpu_forward(torch_cuda):
     import torch
     import paper_2411_00742_amd as pbe
     prob = small_estimation(4, [200, 400, 800, 1000], t_end=600.0)
+    # gamma must stay >= 0 under the -h perturbation
+    prob.par[:, W.P_GAMMA] = np.linspace(2e-4, 1.5e-3, 4)
     s = pbe.Solver(prob, ckpt_every=16)
     o = {k: v.cpu().numpy() for k, v in s.solve().items()}
     tm, tc = o["mom"] * 1.03, o["C"] * 0.999
