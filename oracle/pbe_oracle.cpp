@@ -67,6 +67,9 @@ template <int ND> Dual<ND> log(const Dual<ND>& a) {
 template <int ND> Dual<ND> sin(const Dual<ND>& a) {
     Dual<ND> r(std::sin(a.v)); for (int k = 0; k < ND; ++k) r.d[k] = std::cos(a.v) * a.d[k]; return r;
 }
+template <int ND> Dual<ND> tanh(const Dual<ND>& a) {
+    Dual<ND> r(std::tanh(a.v)); for (int k = 0; k < ND; ++k) r.d[k] = (1.0 - r.v * r.v) * a.d[k]; return r;
+}
 // |x| with derivative sign(x), and 0 at x == 0.
 template <int ND> Dual<ND> fabs(const Dual<ND>& a) {
     if (a.v > 0) return a;
@@ -76,8 +79,17 @@ template <int ND> Dual<ND> fabs(const Dual<ND>& a) {
 
 inline double val(double x) { return x; }
 template <int ND> double val(const Dual<ND>& x) { return x.v; }
+inline void set_tangent(double&, int, double) {}
+template <int ND> void set_tangent(Dual<ND>& x, int k, double v) { if (k >= 0 && k < ND) x.d[k] = v; }
+inline void scale_tangent(double&, double) {}
+template <int ND> void scale_tangent(Dual<ND>& x, double s) { for (int k = 0; k < ND; ++k) x.d[k] *= s; }
 inline double fabs(double x) { return std::fabs(x); }
 inline double exp(double x) { return std::exp(x); }
+inline double log(double x) { return std::log(x); }
+inline double tanh(double x) { return std::tanh(x); }
+// replace the value of x, keeping its derivative (rounding steps are passed through)
+inline double with_value(double, double v) { return v; }
+template <int ND> Dual<ND> with_value(const Dual<ND>& x, double v) { Dual<ND> r = x; r.v = v; return r; }
 
 // x^p for x >= 0 with p > 0: 0 (and zero derivative) at x == 0.
 inline double power(double x, double p) { return x > 0.0 ? std::pow(x, p) : 0.0; }
@@ -144,6 +156,114 @@ void rate_laws(int law, const Kinetics<R>& k, double T, R Sp, R& G0, R& G2, R& B
         G2 = G2 * std::exp(-k.Eg / (T + 273.15));
         B = B * std::exp(-k.Eb / (T + 273.15));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Learned closure (Sec. 4.2, Fig. 5a): a network in place of the rate laws.
+// Layout of the blob and the precision rules are stated in pbe_oracle.h.
+// ---------------------------------------------------------------------------
+constexpr int MH = REF_MLP_H;
+constexpr int OFF_W1 = 0, OFF_B1 = 3 * MH, OFF_W2 = 4 * MH, OFF_B2 = 4 * MH + MH * MH, OFF_W3 = 5 * MH + MH * MH,
+              OFF_B3 = 7 * MH + MH * MH;
+static_assert(OFF_B3 + 2 == REF_MLP_NW, "closure weight count");
+enum { C_IN_SHIFT = 0, C_IN_SCALE = 3, C_OUT_SHIFT = 6, C_OUT_SCALE = 8, C_LO = 10, C_HI = 13, C_SMIN = 16 };
+
+// float -> bfloat16 -> float, round to nearest with ties to even on the 16
+// discarded bits of the IEEE single pattern (finite inputs)
+float round_bf16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+double bf16_of_double(double x) { return (double)round_bf16((float)x); }
+
+template <class R>
+struct Net {
+    int precision = REF_MLP_FP64;
+    std::vector<R> w;        // REF_MLP_NW weights as used (bf16-rounded weight values in BF16 mode)
+    double c[REF_MLP_NC];    // normalisation constants and box
+};
+
+// Weights from the blob; in BF16 mode the matrices (not the biases) are
+// rounded to bfloat16.  dir (may be null) seeds tangent 0 with a direction.
+template <class R>
+Net<R> load_net(const float* blob, int precision, const double* dir, int dir_slot) {
+    Net<R> n;
+    n.precision = precision;
+    n.w.resize(REF_MLP_NW);
+    for (int i = 0; i < REF_MLP_NW; ++i) {
+        const bool is_bias = (i >= OFF_B1 && i < OFF_W2) || (i >= OFF_B2 && i < OFF_W3) || i >= OFF_B3;
+        double v = (double)blob[i];
+        if (precision == REF_MLP_BF16 && !is_bias) v = (double)round_bf16(blob[i]);
+        n.w[i] = R(v);
+        if (dir) set_tangent(n.w[i], dir_slot, dir[i]);
+    }
+    for (int k = 0; k < REF_MLP_NC; ++k) n.c[k] = (double)blob[REF_MLP_NW + k];
+    return n;
+}
+
+// One hidden unit's activation from its pre-activation (exact sum + bias).
+template <class R>
+R activate(const Net<R>& n, const R& pre) {
+    if (n.precision == REF_MLP_FP64) return tanh(pre);
+    const float pf = (float)val(pre);
+    const float t = (float)std::tanh((double)pf);
+    R h = with_value(pre, (double)round_bf16(t));
+    // derivative of tanh at the rounded pre-activation, through the roundings
+    scale_tangent(h, 1.0 - (double)t * (double)t);
+    return h;
+}
+
+// y = W3 tanh(W2 tanh(W1 z + b1) + b2) + b3 on normalised inputs z.
+template <class R>
+void net_forward(const Net<R>& n, const R z[3], R y[2]) {
+    const std::vector<R>& w = n.w;
+    R zi[3];
+    for (int k = 0; k < 3; ++k)
+        zi[k] = n.precision == REF_MLP_BF16 ? with_value(z[k], bf16_of_double((double)(float)val(z[k]))) : z[k];
+    R h1[MH], h2[MH];
+    for (int j = 0; j < MH; ++j) {
+        R a = w[OFF_B1 + j];
+        for (int k = 0; k < 3; ++k) a = a + w[OFF_W1 + j * 3 + k] * zi[k];
+        h1[j] = activate(n, a);
+    }
+    for (int j = 0; j < MH; ++j) {
+        R a = w[OFF_B2 + j];
+        for (int i = 0; i < MH; ++i) a = a + w[OFF_W2 + j * MH + i] * h1[i];
+        h2[j] = activate(n, a);
+    }
+    for (int o = 0; o < 2; ++o) {
+        R a = w[OFF_B3 + o];
+        for (int j = 0; j < MH; ++j) a = a + w[OFF_W3 + o * MH + j] * h2[j];
+        y[o] = n.precision == REF_MLP_BF16 ? with_value(a, (double)(float)val(a)) : a;
+    }
+}
+
+// Closure rates at supersaturation S (not clipped), temperature T and second
+// moment mu2.  Returns true when the plain power law was used instead.
+template <class R>
+bool closure_rates(const Net<R>& n, const Kinetics<R>& k, const R& S, double T, const R& mu2, R& G0, R& B) {
+    const double* c = n.c;
+    bool inside = val(S) > c[C_SMIN] && val(mu2) > 0.0;
+    R x[3] = {S, R(T), R(0.0)};
+    if (inside) x[2] = log(mu2) / std::log(10.0);
+    for (int q = 0; q < 3 && inside; ++q) inside = val(x[q]) >= c[C_LO + q] && val(x[q]) <= c[C_HI + q];
+    if (!inside) {
+        const R Sp = val(S) > 0.0 ? S : R(0.0);
+        G0 = 1e6 * k.kg * power(Sp, k.g);
+        B = k.kb * power(Sp, k.b);
+        return true;
+    }
+    R z[3], y[2];
+    for (int q = 0; q < 3; ++q) z[q] = (x[q] - c[C_IN_SHIFT + q]) * c[C_IN_SCALE + q];
+    net_forward(n, z, y);
+    G0 = exp(c[C_OUT_SHIFT] + c[C_OUT_SCALE] * y[0]);
+    B = exp(c[C_OUT_SHIFT + 1] + c[C_OUT_SCALE + 1] * y[1]);
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -282,7 +402,8 @@ struct Tangents {
 };
 
 template <class R>
-int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tangents<R>* tan_out) {
+int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tangents<R>* tan_out,
+                 const Net<R>* net = nullptr) {
     const int n = s->n;
     const double dL = s->L_max / n;
     std::vector<R> f(n);
@@ -312,7 +433,12 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
         const double Csat = solubility(p, T);
         const R Sp = supersaturation_pos(C, Csat);
         R G0, G2, B;
-        rate_laws(p->law, k, T, Sp, G0, G2, B);
+        if (p->law == REF_LAW_MLP) {
+            // closure inputs: supersaturation, temperature and mu_2 of the current state
+            if (closure_rates(*net, k, C / Csat - 1.0, T, moment1d(f, n, dL, 2), G0, B)) status |= REF_SIM_FALLBACK;
+        } else {
+            rate_laws(p->law, k, T, Sp, G0, G2, B);
+        }
 
         const double t_next = next < s->n_samples ? s->t_samples[next] : p->t_end;
         const double Gmax = val(G0) * (1.0 + val(k.gamma) * s->L_max);
@@ -565,7 +691,11 @@ double ref_limited_slope(double a, double b) { return limited_slope<double>(a, b
 
 int ref_solve1d(const ref_process* p, ref_sim1d* s) {
     if (!p || !s || s->n < 1 || !s->f0 || !s->par) return -1;
-    if (p->law == REF_LAW_MLP) return -2;
+    if (p->law == REF_LAW_MLP) {
+        if (!p->mlp) return -1;
+        const Net<double> net = load_net<double>(p->mlp, p->mlp_precision, nullptr, -1);
+        return solve1d_impl<double>(p, s, load_kinetics<double>(s->par), nullptr, &net);
+    }
     return solve1d_impl<double>(p, s, load_kinetics<double>(s->par), nullptr);
 }
 
@@ -615,6 +745,124 @@ int ref_tangent1d(const ref_process* p, ref_sim1d* s, double* dF, double* dM, do
                 for (int i = 0; i < s->n; ++i) dF[((size_t)q * s->n + i) * REF_NTAN + d] = tf[(size_t)q * s->n + i].d[d];
         }
     }
+    return 0;
+}
+
+double ref_bf16(double x) { return bf16_of_double(x); }
+
+int ref_mlp_forward(const float* blob, int32_t precision, int32_t n, const double* x, double* y, double* dy) {
+    typedef Dual<3> D;
+    if (!blob || n < 0 || !x || !y) return -1;
+    const Net<D> net = load_net<D>(blob, precision, nullptr, -1);
+    for (int r = 0; r < n; ++r) {
+        D z[3], o[2];
+        for (int q = 0; q < 3; ++q) {
+            z[q] = D((x[r * 3 + q] - net.c[C_IN_SHIFT + q]) * net.c[C_IN_SCALE + q]);
+            z[q].d[q] = 1.0;
+        }
+        net_forward(net, z, o);
+        for (int j = 0; j < 2; ++j) {
+            y[r * 2 + j] = o[j].v;
+            if (dy)
+                for (int q = 0; q < 3; ++q) dy[(r * 2 + j) * 3 + q] = o[j].d[q];
+        }
+    }
+    return 0;
+}
+
+// Reverse pass of the network written out layer by layer (the transposed
+// products of the forward pass); the roundings of BF16 mode act on values only.
+int ref_mlp_vjp(const float* blob, int32_t precision, int32_t n, const double* z, const double* ybar, double* gw) {
+    if (!blob || n < 0 || !z || !ybar || !gw) return -1;
+    const Net<double> net = load_net<double>(blob, precision, nullptr, -1);
+    const std::vector<double>& w = net.w;
+    const bool bf = precision == REF_MLP_BF16;
+    for (int i = 0; i < REF_MLP_NW; ++i) gw[i] = 0.0;
+    for (int r = 0; r < n; ++r) {
+        double zi[3], a1[MH], h1[MH], t1[MH], a2[MH], h2[MH], t2[MH];
+        for (int k = 0; k < 3; ++k) zi[k] = bf ? bf16_of_double((double)(float)z[r * 3 + k]) : z[r * 3 + k];
+        for (int j = 0; j < MH; ++j) {
+            double a = w[OFF_B1 + j];
+            for (int k = 0; k < 3; ++k) a += w[OFF_W1 + j * 3 + k] * zi[k];
+            a1[j] = a;
+            t1[j] = bf ? (double)(float)std::tanh((double)(float)a) : std::tanh(a);
+            h1[j] = bf ? (double)round_bf16((float)t1[j]) : t1[j];
+        }
+        for (int j = 0; j < MH; ++j) {
+            double a = w[OFF_B2 + j];
+            for (int i = 0; i < MH; ++i) a += w[OFF_W2 + j * MH + i] * h1[i];
+            a2[j] = a;
+            t2[j] = bf ? (double)(float)std::tanh((double)(float)a) : std::tanh(a);
+            h2[j] = bf ? (double)round_bf16((float)t2[j]) : t2[j];
+        }
+        (void)a1; (void)a2;
+        const double yb[2] = {ybar[r * 2], ybar[r * 2 + 1]};
+        double d2[MH], d1[MH];
+        for (int o = 0; o < 2; ++o) {
+            gw[OFF_B3 + o] += yb[o];
+            for (int j = 0; j < MH; ++j) gw[OFF_W3 + o * MH + j] += yb[o] * h2[j];
+        }
+        for (int j = 0; j < MH; ++j) {
+            double g = 0.0;
+            for (int o = 0; o < 2; ++o) g += w[OFF_W3 + o * MH + j] * yb[o];
+            d2[j] = g * (1.0 - t2[j] * t2[j]);
+        }
+        for (int j = 0; j < MH; ++j) {
+            gw[OFF_B2 + j] += d2[j];
+            for (int i = 0; i < MH; ++i) gw[OFF_W2 + j * MH + i] += d2[j] * h1[i];
+        }
+        for (int i = 0; i < MH; ++i) {
+            double g = 0.0;
+            for (int j = 0; j < MH; ++j) g += w[OFF_W2 + j * MH + i] * d2[j];
+            d1[i] = g * (1.0 - t1[i] * t1[i]);
+        }
+        for (int j = 0; j < MH; ++j) {
+            gw[OFF_B1 + j] += d1[j];
+            for (int k = 0; k < 3; ++k) gw[OFF_W1 + j * 3 + k] += d1[j] * zi[k];
+        }
+    }
+    return 0;
+}
+
+int ref_tangent1d_mlp(const ref_process* p, ref_sim1d* s, const double* v, double* dF, double* dM, double* dC) {
+    typedef Dual<2> D;
+    if (!p || !s || s->n < 1 || p->law != REF_LAW_MLP || !p->mlp || !v) return -1;
+    const Net<double> net0 = load_net<double>(p->mlp, p->mlp_precision, nullptr, -1);
+    const int cap = s->max_steps > 0 ? s->max_steps : 2000000;
+    std::vector<double> dts(std::min(cap, 2000000));
+    int steps = 0;
+    {
+        ref_sim1d s0 = *s;
+        s0.f_samples = nullptr; s0.mom = nullptr; s0.C = nullptr; s0.f_final = nullptr;
+        s0.G0_log = nullptr; s0.B_log = nullptr; s0.outflow = nullptr;
+        s0.C_final = nullptr; s0.t_final = nullptr; s0.status = nullptr;
+        s0.dt_log = dts.data();
+        s0.steps = &steps;
+        s0.max_steps = (int)dts.size();
+        solve1d_impl<double>(p, &s0, load_kinetics<double>(s0.par), nullptr, &net0);
+        dts.resize(steps);
+    }
+    const Net<D> net = load_net<D>(p->mlp, p->mlp_precision, v, 0);
+    Kinetics<D> k = load_kinetics<D>(s->par);
+    k.gamma.d[1] = 1.0;
+    std::vector<D> tf((size_t)s->n_samples * s->n), tm((size_t)s->n_samples * 4), tc(s->n_samples);
+    Tangents<D> tan;
+    tan.f_samples = dF ? &tf : nullptr;
+    tan.mom = &tm;
+    tan.C = &tc;
+    ref_sim1d s1 = *s;
+    s1.dt_replay = dts.data();
+    s1.n_replay = steps;
+    s1.max_steps = steps;
+    solve1d_impl<D>(p, &s1, k, &tan, &net);
+    for (int q = 0; q < s->n_samples; ++q)
+        for (int d = 0; d < 2; ++d) {
+            if (dC) dC[q * 2 + d] = tc[q].d[d];
+            for (int m = 0; m < 4; ++m)
+                if (dM) dM[(q * 4 + m) * 2 + d] = tm[q * 4 + m].d[d];
+            if (dF)
+                for (int i = 0; i < s->n; ++i) dF[((size_t)q * s->n + i) * 2 + d] = tf[(size_t)q * s->n + i].d[d];
+        }
     return 0;
 }
 

@@ -46,12 +46,34 @@ enum { REF_LAW_POWER = 0, REF_LAW_ARRHENIUS = 1, REF_LAW_MLP = 2 };
 enum { REF_SOL_LINEAR = 0, REF_SOL_EXP = 1 };
 enum { REF_SIM_OK = 0, REF_SIM_NONFINITE = 1, REF_SIM_OUTFLOW = 2, REF_SIM_FALLBACK = 4 };
 
+/* Learned closure (Sec. 4.2, Fig. 5a: a network replaces the advection-rate
+ * computation of the loop in Fig. 1).  Blob of REF_MLP_NBLOB floats:
+ *   W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]        (REF_MLP_NW weights)
+ *   in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
+ * Inputs x = (S, T [degC], log10 mu_2) with S = C/Csat - 1, normalised as
+ * z_k = (x_k - in_shift_k) * in_scale_k;  h1 = tanh(W1 z + b1),
+ * h2 = tanh(W2 h1 + b2), y = W3 h2 + b3;  ln G0 = out_shift_0 + out_scale_0 y_0
+ * (G0 in um/s) and ln B = out_shift_1 + out_scale_1 y_1.  Where S <= s_min,
+ * mu_2 <= 0 or some x_k lies outside [lo_k, hi_k], the plain power law with the
+ * simulation's (kg, g, kb, b) is used instead and REF_SIM_FALLBACK is set.
+ * Precision REF_MLP_FP64: all in double.  REF_MLP_BF16: z, the weights and the
+ * hidden activations are rounded to bfloat16 (round to nearest even, z going
+ * through float first), each pre-activation is the exact sum plus the float
+ * bias rounded once to float, tanh is rounded to float before the bfloat16
+ * rounding, and y is rounded to float.  Derivatives pass through the roundings
+ * unchanged, with tanh' = 1 - t^2 at the float value t. */
+#define REF_MLP_H 64
+#define REF_MLP_NW 4546
+#define REF_MLP_NC 17
+#define REF_MLP_NBLOB (REF_MLP_NW + REF_MLP_NC)
+enum { REF_MLP_BF16 = 0, REF_MLP_FP64 = 1 };
+
 typedef struct {
-    int32_t law, scheme, sol_law, pad_;
+    int32_t law, scheme, sol_law, mlp_precision;
     double cs0, cs1;          /* Csat = cs0 + cs1*T (linear) or cs0*exp(cs1*T) */
     double alpha;             /* rho_c * k_v / rho_solvent, g/g per (um^3/m^3) */
     double cfl, dt_max, t_end;
-    const float *mlp;         /* law == REF_LAW_MLP: packed closure weights (see ref_mlp_*) */
+    const float *mlp;         /* law == REF_LAW_MLP: closure blob [REF_MLP_NBLOB] */
 } ref_process;
 
 /* One 1D simulation.  Inputs first, then optional outputs (NULL = skip). */
@@ -104,6 +126,19 @@ int ref_solve1d_batch(const ref_process *p, ref_sim1d *sims, int32_t n_sims, int
  * with the step-size schedule of the primal run held fixed.
  * dF [n_samples][n][5], dM [n_samples][4][5], dC [n_samples][5] (each may be NULL). */
 int ref_tangent1d(const ref_process *p, ref_sim1d *s, double *dF, double *dM, double *dC);
+
+/* (double)(bfloat16)(float)x with round-to-nearest-even at both steps. */
+double ref_bf16(double x);
+/* Closure network alone on n inputs x[n][3] = (S, T, log10 mu_2), ignoring the
+ * box: y[n][2]; dy[n][2][3] = dy/dz (may be NULL). */
+int ref_mlp_forward(const float *blob, int32_t precision, int32_t n, const double *x, double *y, double *dy);
+/* Weight gradient of sum_r ybar[r] . y(z[r]) over n rows of normalised inputs
+ * z[n][3]: gw[REF_MLP_NW], same order as the blob's weights. */
+int ref_mlp_vjp(const float *blob, int32_t precision, int32_t n, const double *z, const double *ybar, double *gw);
+/* Learned-closure solve: forward-mode derivatives along the weight direction
+ * v[REF_MLP_NW] (tangent 0) and along gamma (tangent 1), step schedule of the
+ * primal run held fixed.  dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
+int ref_tangent1d_mlp(const ref_process *p, ref_sim1d *s, const double *v, double *dF, double *dM, double *dC);
 
 int ref_solve2d(const ref_process *p, ref_sim2d *s);
 int ref_solve2d_batch(const ref_process *p, ref_sim2d *sims, int32_t n_sims, int32_t n_threads);

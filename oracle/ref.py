@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
 
 
 class Process(C.Structure):
-    _fields_ = [("law", C.c_int32), ("scheme", C.c_int32), ("sol_law", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("law", C.c_int32), ("scheme", C.c_int32), ("sol_law", C.c_int32), ("mlp_precision", C.c_int32),
                 ("cs0", C.c_double), ("cs1", C.c_double), ("alpha", C.c_double),
                 ("cfl", C.c_double), ("dt_max", C.c_double), ("t_end", C.c_double),
                 ("mlp", C.POINTER(C.c_float))]
@@ -83,6 +83,12 @@ def lib():
                                 _dp, _dp]
         L.ref_mom2d.argtypes = L.ref_mom1d.argtypes
         L.ref_dual_example.argtypes = [C.c_double, C.c_double, _dp]
+        L.ref_bf16.restype = C.c_double
+        L.ref_bf16.argtypes = [C.c_double]
+        _fp = C.POINTER(C.c_float)
+        L.ref_mlp_forward.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
+        L.ref_mlp_vjp.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
+        L.ref_tangent1d_mlp.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -96,8 +102,14 @@ def _ptr(a):
 
 
 def process_of(prob) -> Process:
-    return Process(law=prob.law, scheme=prob.scheme, sol_law=prob.sol_law, pad_=0, cs0=prob.cs0, cs1=prob.cs1,
-                   alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max, t_end=prob.t_end, mlp=None)
+    """Process struct for a Problem; for the closure law it points into prob.mlp (kept alive by prob)."""
+    mlp = None
+    if getattr(prob, "mlp", None) is not None:
+        assert prob.mlp.dtype == np.float32 and prob.mlp.flags.c_contiguous
+        mlp = prob.mlp.ctypes.data_as(C.POINTER(C.c_float))
+    return Process(law=prob.law, scheme=prob.scheme, sol_law=prob.sol_law,
+                   mlp_precision=int(getattr(prob, "mlp_precision", 0)), cs0=prob.cs0, cs1=prob.cs1,
+                   alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max, t_end=prob.t_end, mlp=mlp)
 
 
 def phi_vanleer(theta: float) -> float:
@@ -291,3 +303,50 @@ def mom2d(prob, s: int, mu_init, t_samples=None, rtol: float = 1e-12, atol: floa
     if rc != 0:
         raise RuntimeError("ref_mom2d did not converge")
     return mu, Cq
+
+
+def _blob(w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    return w, w.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def mlp_forward(blob, precision: int, x, with_jac: bool = False):
+    """Closure network on raw inputs x[n, 3] = (S, T, log10 mu_2): y[n, 2] (and dy/dz [n, 2, 3])."""
+    w, wp = _blob(blob)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    n = x.shape[0]
+    y = np.zeros((n, 2))
+    dy = np.zeros((n, 2, 3)) if with_jac else None
+    rc = lib().ref_mlp_forward(wp, precision, n, _ptr(x), _ptr(y), _ptr(dy))
+    assert rc == 0
+    return (y, dy) if with_jac else y
+
+
+def mlp_vjp(blob, precision: int, z, ybar):
+    """Weight gradient of sum_r ybar[r] . y(z[r]) for normalised inputs z[n, 3]."""
+    w, wp = _blob(blob)
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, 3)
+    ybar = np.ascontiguousarray(ybar, dtype=np.float64).reshape(-1, 2)
+    g = np.zeros(4546)
+    rc = lib().ref_mlp_vjp(wp, precision, z.shape[0], _ptr(z), _ptr(ybar), _ptr(g))
+    assert rc == 0
+    return g
+
+
+def tangent1d_mlp(prob, s: int, v, with_f: bool = True, max_steps: int | None = None):
+    """Closure-law solve: derivatives along the weight direction v (tangent 0) and gamma (tangent 1)."""
+    n, ns = int(prob.n_cells[s]), len(prob.t_samples)
+    b = _Sim1DBuffers(prob, s, False, max_steps, None, 0)
+    st = b.struct
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    dF = np.zeros((ns, n, 2)) if with_f else None
+    dM = np.zeros((ns, 4, 2))
+    dC = np.zeros((ns, 2))
+    p = process_of(prob)
+    rc = lib().ref_tangent1d_mlp(C.byref(p), C.byref(st), _ptr(v), _ptr(dF), _ptr(dM), _ptr(dC))
+    assert rc == 0, rc
+    return dict(dF=dF, dM=dM, dC=dC)
+
+
+def bf16(x: float) -> float:
+    return lib().ref_bf16(float(x))

@@ -148,6 +148,8 @@ class Problem:
     t_end: float = T_END
     name: str = ""
     extra: dict = field(default_factory=dict)
+    mlp: np.ndarray | None = None      # law == LAW_MLP: float32 closure blob [MLP_NBLOB]
+    mlp_precision: int = 0             # MLP_BF16 or MLP_FP64
 
     @property
     def n_sims(self) -> int:
@@ -310,6 +312,46 @@ def estimation(n_sims: int = 1024, n: int = 1000, t_end: float = T_END, n_sample
                    t_samples=uniform_samples(n_samples, t_end), t_end=t_end,
                    name=f"estimation-{n_sims}xN{n}")
     return prob, np.array(truth), noise
+
+
+# closure network blob: W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2], then
+# in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
+MLP_H = 64
+MLP_NW = 4546
+MLP_NC = 17
+MLP_NBLOB = MLP_NW + MLP_NC
+MLP_BF16, MLP_FP64 = 0, 1
+MLP_OFF = dict(W1=0, b1=192, W2=256, b2=4352, W3=4416, b3=4544)
+
+
+def closure_consts(in_shift=(0.1, 30.0, 14.0), in_scale=(10.0, 0.1, 1.0), out_shift=(-4.0, 17.0),
+                   out_scale=(2.0, 2.0), lo=(0.0, -10.0, 6.0), hi=(2.0, 80.0, 22.0), s_min=1e-8) -> np.ndarray:
+    """Normalisation and validity box of the closure inputs (S, T degC, log10 mu_2).
+
+    Defaults fit the closure workload: S up to ~0.3, T in 15..40 degC, mu_2 of
+    the seed ~4e13 um^2/m^3 growing to ~1e15; ln G0 ~ -4 (G0 ~ 0.02 um/s) and
+    ln B ~ 17 (B ~ 2e7 #/(m^3 s)).
+    """
+    return np.array(list(in_shift) + list(in_scale) + list(out_shift) + list(out_scale) + list(lo) + list(hi)
+                    + [s_min], dtype=np.float32)
+
+
+def closure_net(seed_offset: int = 5, out_gain: float = 0.1, consts=None) -> np.ndarray:
+    """Initial closure weights: Glorot-uniform matrices from the seeded generator
+    (the output layer scaled by out_gain), zero biases, then the constants."""
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    w = np.zeros(MLP_NBLOB, dtype=np.float32)
+
+    def glorot(n_out, n_in, gain=1.0):
+        a = gain * math.sqrt(6.0 / (n_in + n_out))
+        return np.array([rng.uniform_range(-a, a) for _ in range(n_out * n_in)], dtype=np.float32)
+
+    o = MLP_OFF
+    w[o["W1"]:o["W1"] + 192] = glorot(64, 3)
+    w[o["W2"]:o["W2"] + 4096] = glorot(64, 64)
+    w[o["W3"]:o["W3"] + 128] = glorot(2, 64, out_gain)
+    w[MLP_NW:] = closure_consts() if consts is None else consts
+    return w
 
 
 def closure(n_sims: int = 4096, n: int = 500, t_end: float = T_END, n_samples: int = 20,
