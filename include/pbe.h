@@ -61,6 +61,23 @@ enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G
        PBE_P_T0, PBE_P_T1, PBE_P_TRAMP, PBE_NPAR };
 #define PBE_NGRAD 5   /* pbe_grad returns d/d(kg, g, kb, b, gamma) per sim */
 
+/* Learned closure (law PBE_LAW_MLP): the empirical hybrid model of Sec. 4.2,
+ * Fig. 5a, in which a network replaces the growth/nucleation rate laws.
+ * Blob of PBE_MLP_NW weights then PBE_MLP_NC constants (float):
+ *   W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]
+ *   in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
+ * Inputs x = (S, T [degC], log10 mu_2) with S = C/Csat - 1 and mu_2 of the
+ * current state; z = (x - in_shift) * in_scale; h1 = tanh(W1 z + b1),
+ * h2 = tanh(W2 h1 + b2), y = W3 h2 + b3; ln G0 = out_shift0 + out_scale0 y0
+ * (G0 in um/s) and ln B = out_shift1 + out_scale1 y1.  Where S <= s_min,
+ * mu_2 <= 0 or x leaves [lo, hi], the power law with the sim's (kg, g, kb, b)
+ * is used and PBE_SIM_FALLBACK is set.  PBE_MLP_BF16: bfloat16 weights and
+ * activations on the matrix cores with fp32 accumulation; PBE_MLP_FP64: fp64.
+ * The closure runs the SSP-RK3 scheme on grids of up to 1024 cells. */
+#define PBE_MLP_NW 4546
+#define PBE_MLP_NC 17
+enum { PBE_MLP_BF16 = 0, PBE_MLP_FP64 = 1 };
+
 typedef struct {
     int32_t ndim;               /* 1 or 2 */
     int32_t n_sims;             /* S >= 1 */
@@ -70,7 +87,8 @@ typedef struct {
     const double *C0;           /* host [S] initial concentration */
     const double *par;          /* host [S*PBE_NPAR] kinetics and the cooling ramp
                                    T(t) = T0 + (T1 - T0) min(t, t_ramp)/t_ramp */
-    const float *mlp;           /* host, law == PBE_LAW_MLP only: closure weights (pbe_mlp_nparams floats) */
+    const float *mlp;           /* host, law == PBE_LAW_MLP only: closure blob of PBE_MLP_NW + PBE_MLP_NC
+                                   floats (layout below); copied at create */
     int32_t law, scheme, sol_law;
     int32_t n_samples;          /* >= 1 */
     double cs0, cs1;            /* solubility coefficients */
@@ -82,7 +100,7 @@ typedef struct {
     int32_t ckpt_every;         /* 0: no gradients; K > 0: checkpoint every K steps for pbe_grad (1D) */
     int32_t max_steps;          /* per-sim step budget (0: derived from t_end, dt_max and the CFL bound) */
     int32_t flags;              /* PBE_FLAG_* */
-    int32_t reserved;
+    int32_t mlp_precision;      /* law == PBE_LAW_MLP: PBE_MLP_BF16 or PBE_MLP_FP64 */
 } pbe_problem;
 
 /* Create a handle: validates `p`, deep-copies every input to device memory
@@ -126,12 +144,35 @@ int pbe_fetch(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
  * given cotangents gf (shape of f_out), gmom (shape of mom_out), gC (shape
  * of C_out) - each may be NULL for zero - write
  *   gpar_out  [S][PBE_NGRAD] = d<cot, outputs>/d(kg, g, kb, b, gamma) per sim,
- *   gmlp_out  law == MLP: d/d(closure weights) summed over sims (fp32), else unused.
+ *   gmlp_out  law == MLP: [PBE_MLP_NW] d<cot, outputs>/d(closure weights), summed over sims
+ *             (may be NULL); ignored for other laws.
  * The step-size schedule of the forward solve is held fixed (it is not
  * differentiated).  Requires ckpt_every > 0 and a completed pbe_solve
  * (PBE_ESTATE otherwise). */
 int pbe_grad(pbe_handle *h, const double *gf, const double *gmom, const double *gC,
-             double *gpar_out, float *gmlp_out);
+             double *gpar_out, double *gmlp_out);
+
+/* Replace the closure weights (law == MLP) with w[PBE_MLP_NW] (host pointer,
+ * or device pointer with PBE_FLAG_DEVICE_PTRS; the blob's constants are kept)
+ * and restart from the initial condition.  Ordered on the handle's stream
+ * after its queued work; non-finite weights give PBE_EINVAL (host pointers only
+ * are checked).  PBE_ESTATE for other laws. */
+int pbe_set_mlp(pbe_handle *h, const float *w);
+
+/* The closure network alone (no box, no rates): for raw inputs
+ * x[n][3] = (S, T, log10 mu_2) writes y[n][2] (the two network outputs) and
+ * dy[n][2][2] = dy_o/d(z0, z2) of the normalised inputs.  x, y, dy are device
+ * pointers ordered on hip_stream; blob is a host closure blob.  Blocks until
+ * done (it copies the blob in and frees its scratch). */
+int pbe_mlp_forward(const float *blob, int32_t precision, int32_t n, const double *x, double *y, double *dy,
+                    void *hip_stream);
+
+/* One Adam step (Kingma and Ba; the optimiser of Sec. 4.1 / App. C) on device
+ * arrays of n floats: w -= lr * mhat / (sqrt(vhat) + eps) with the moment
+ * estimates m, v updated from the gradient g (device, double) and bias
+ * correction for step >= 1.  Ordered on hip_stream, does not wait. */
+int pbe_adam(float *w, float *m, float *v, const double *g, int32_t n, int32_t step, float lr, float beta1,
+             float beta2, float eps, void *hip_stream);
 
 /* Replace every sim's parameter row (host pointer [S*PBE_NPAR], same checks
  * as pbe_create) without rebuilding the handle, e.g. between optimizer

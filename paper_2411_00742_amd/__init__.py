@@ -26,7 +26,9 @@ NGRAD = 5
 
 # every entry point of include/pbe.h
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
-           "pbe_destroy", "pbe_strerror", "pbe_last_kernel_ms"]
+           "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_destroy", "pbe_strerror", "pbe_last_kernel_ms"]
+MLP_NW, MLP_NC = 4546, 17
+MLP_BF16, MLP_FP64 = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -40,7 +42,7 @@ class PbeProblem(C.Structure):
                 ("cs0", C.c_double), ("cs1", C.c_double), ("alpha", C.c_double), ("cfl", C.c_double),
                 ("dt_max", C.c_double), ("t_end", C.c_double), ("t_samples", _dp),
                 ("ckpt_every", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("mlp_precision", C.c_int32)]
 
 
 class PBEError(RuntimeError):
@@ -68,6 +70,9 @@ def lib():
         L.pbe_fetch.argtypes = [vp, vp, vp, vp, vp, vp]
         L.pbe_grad.argtypes = [vp, vp, vp, vp, vp, vp]
         L.pbe_set_par.argtypes = [vp, _dp]
+        L.pbe_set_mlp.argtypes = [vp, vp]
+        L.pbe_mlp_forward.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
+        L.pbe_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.pbe_destroy.argtypes = [vp]
         L.pbe_destroy.restype = None
         L.pbe_strerror.argtypes = [C.c_int]
@@ -94,15 +99,20 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
     keep = dict(n_cells=_arr(prob.n_cells.reshape(-1), np.int32), L_max=_arr(prob.L_max.reshape(-1), np.float64),
                 f0=_arr(prob.f0, np.float64), C0=_arr(prob.C0, np.float64), par=_arr(prob.par, np.float64),
                 t_samples=_arr(prob.t_samples, np.float64))
+    mlp = getattr(prob, "mlp", None)
+    if mlp is not None:
+        keep["mlp"] = _arr(mlp, np.float32)
     flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0)
     st = PbeProblem(ndim=prob.ndim, n_sims=prob.n_sims,
                     n_cells=keep["n_cells"].ctypes.data_as(_ip), L_max=keep["L_max"].ctypes.data_as(_dp),
                     f0=keep["f0"].ctypes.data_as(_dp), C0=keep["C0"].ctypes.data_as(_dp),
-                    par=keep["par"].ctypes.data_as(_dp), mlp=None,
+                    par=keep["par"].ctypes.data_as(_dp),
+                    mlp=keep["mlp"].ctypes.data_as(C.POINTER(C.c_float)) if "mlp" in keep else None,
                     law=prob.law, scheme=prob.scheme, sol_law=prob.sol_law, n_samples=len(prob.t_samples),
                     cs0=prob.cs0, cs1=prob.cs1, alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max,
                     t_end=prob.t_end, t_samples=keep["t_samples"].ctypes.data_as(_dp),
-                    ckpt_every=ckpt_every, max_steps=max_steps, flags=flags, reserved=0)
+                    ckpt_every=ckpt_every, max_steps=max_steps, flags=flags,
+                    mlp_precision=int(getattr(prob, "mlp_precision", 0)))
     return st, keep
 
 
@@ -170,13 +180,23 @@ class Solver:
         assert p.shape == (self.S, NPAR)
         _check(lib().pbe_set_par(self._h, p.ctypes.data_as(_dp)), "pbe_set_par")
 
-    def grad(self, gf=None, gmom=None, gC=None):
-        """d<cotangents, outputs>/d(kg, g, kb, b, gamma) per sim, as a [S, 5] device tensor."""
+    def grad(self, gf=None, gmom=None, gC=None, with_mlp: bool = False):
+        """d<cotangents, outputs>/d(kg, g, kb, b, gamma) per sim, as a [S, 5] device tensor;
+        with_mlp (closure law): also d/d(closure weights) [MLP_NW], summed over sims."""
         t = self.torch
         g = t.empty((self.S, NGRAD), dtype=t.float64, device=self.device)
+        gw = t.empty(MLP_NW, dtype=t.float64, device=self.device) if with_mlp else None
         cot = [None if x is None else x.to(device=self.device, dtype=t.float64).contiguous() for x in (gf, gmom, gC)]
-        _check(lib().pbe_grad(self._h, _ptr(cot[0]), _ptr(cot[1]), _ptr(cot[2]), _ptr(g), None), "pbe_grad")
-        return g
+        _check(lib().pbe_grad(self._h, _ptr(cot[0]), _ptr(cot[1]), _ptr(cot[2]), _ptr(g), _ptr(gw)), "pbe_grad")
+        return (g, gw) if with_mlp else g
+
+    def set_mlp(self, w):
+        """New closure weights: a float32 device tensor (or array) of MLP_NW values."""
+        t = self.torch
+        w = t.as_tensor(w, dtype=t.float32).to(self.device).contiguous()
+        assert w.numel() == MLP_NW
+        _check(lib().pbe_set_mlp(self._h, _ptr(w)), "pbe_set_mlp")
+        self._mlp_keep = w
 
     def last_kernel_ms(self):
         a, b = C.c_float(), C.c_float()
@@ -193,6 +213,43 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def mlp_forward(blob, precision: int, x):
+    """The closure network on raw inputs x[n, 3] = (S, T, log10 mu_2) (device tensor or array):
+    returns device tensors y [n, 2] and dy [n, 2, 2] = dy/d(z0, z2)."""
+    import torch
+    b = _arr(blob, np.float32)
+    assert b.size == MLP_NW + MLP_NC
+    dev = torch.device("cuda", torch.cuda.current_device())
+    xt = torch.as_tensor(x, dtype=torch.float64).to(dev).contiguous().reshape(-1, 3)
+    n = xt.shape[0]
+    y = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    dy = torch.empty((n, 2, 2), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream()
+    _check(lib().pbe_mlp_forward(b.ctypes.data_as(C.POINTER(C.c_float)), precision, n, _ptr(xt), _ptr(y), _ptr(dy),
+                                 C.c_void_p(st.cuda_stream)), "pbe_mlp_forward")
+    return y, dy
+
+
+class Adam:
+    """Adam state for a float32 device parameter vector, stepped by the library's kernel."""
+
+    def __init__(self, w, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        self.w = w
+        self.m = torch.zeros_like(w)
+        self.v = torch.zeros_like(w)
+        self.lr, self.b1, self.b2, self.eps = lr, beta1, beta2, eps
+        self.t = 0
+
+    def step(self, g):
+        import torch
+        self.t += 1
+        g = g.to(dtype=torch.float64).contiguous()
+        st = torch.cuda.current_stream()
+        _check(lib().pbe_adam(_ptr(self.w), _ptr(self.m), _ptr(self.v), _ptr(g), self.w.numel(), self.t, self.lr,
+                              self.b1, self.b2, self.eps, C.c_void_p(st.cuda_stream)), "pbe_adam")
 
 
 def _autograd_function():

@@ -16,6 +16,7 @@
 //      the rate laws, adding sample cotangents as their steps are reached.
 // Derivative conventions: the limited slope psi = 2ab/(a+b) for ab > 0 has
 // zero derivative where ab <= 0; max(S, 0) and S^p have zero derivative at S <= 0.
+#include "closure_device.h"
 #include "fvm1d_device.h"
 #include "pbe_internal.h"
 
@@ -116,7 +117,7 @@ __device__ __forceinline__ int samples_reached(const double* ts, int ns, double 
     return uniform(n);
 }
 
-template <int K>
+template <int K, int CL>
 __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* __restrict__ lds) {
     const Fvm1dArgs& a = A.fw;
     const int lane = threadIdx.x;
@@ -156,6 +157,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     double* tape = A.tape + base * Kc;
     double* tapeC = A.tape_C + (int64_t)s * Kc;
     double* tapeT = A.tape_t + (int64_t)s * Kc;
+    double* tapeR = A.tape_r + (int64_t)s * Kc * kClosureTape;
+    double* rows = A.rows + (int64_t)s * A.row_cap * 5;
 
     const int n_seg = (n_total + Kc - 1) / Kc;
     for (int seg = n_seg - 1; seg >= 0; --seg) {
@@ -176,7 +179,26 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 tapeC[m - m0] = C;
                 tapeT[m - m0] = t;
             }
-            const Rates r = rates_plain(p, q, C, t);
+            Rates r;
+            if constexpr (CL == kClosureNone) {
+                r = rates_plain(p, q, C, t);
+            } else {
+                // closure with the forward tangents d/dz0, d/dz2; taped for the reverse walk
+                LaneGeom g2 = g;
+                asm volatile("" : "+v"(g2.xb));
+                const double mu2 = wave_sum(lane_moment2(u, g2, dL)) * dL;
+                const ClosureRates cr = closure_rates<true, CL>(a.cd, p, q, C, t, mu2);
+                r.G0 = cr.G0;
+                r.B = cr.B;
+                if (lane == 0) {
+                    double* tr = tapeR + (int64_t)(m - m0) * kClosureTape;
+                    tr[0] = cr.fallback ? 1.0 : 0.0;
+                    tr[1] = cr.G0; tr[2] = cr.B;
+                    tr[3] = cr.z[0]; tr[4] = cr.z[1]; tr[5] = cr.z[2];
+                    tr[6] = cr.dy[0][0]; tr[7] = cr.dy[1][0]; tr[8] = cr.dy[0][1]; tr[9] = cr.dy[1][1];
+                    tr[10] = mu2;
+                }
+            }
             const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
             double dt;
             const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
@@ -228,7 +250,29 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             const double Cm = uniform(tapeC[m - 1 - m0]);
             const double tm = uniform(tapeT[m - 1 - m0]);
             const int nx = samples_reached(ts, ns, tm);
-            const Rates r = rates_plain(p, q, Cm, tm);
+            Rates r;
+            bool fb = true;   // plain power law at this step
+            double cz[3] = {0.0, 0.0, 0.0}, cj[4] = {0.0, 0.0, 0.0, 0.0}, cmu2 = 0.0;
+            if constexpr (CL == kClosureNone) {
+                r = rates_plain(p, q, Cm, tm);
+            } else {
+                const double* tr = tapeR + (int64_t)(m - 1 - m0) * kClosureTape;
+                fb = uniform(tr[0]) != 0.0;
+                if (fb) {
+                    const Process pp{PBE_LAW_POWER, p.scheme, p.sol_law, p.cs0, p.cs1, p.alpha, p.cfl, p.dt_max,
+                                     p.t_end};
+                    r = rates_plain(pp, q, Cm, tm);
+                } else {
+                    r.G0 = uniform(tr[1]);
+                    r.B = uniform(tr[2]);
+                    r.S = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) cz[i] = uniform(tr[3 + i]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cj[i] = uniform(tr[6 + i]);
+                    cmu2 = uniform(tr[10]);
+                }
+            }
             const double t_next = uniform(nx < ns ? ts[min(nx, ns - 1)] : p.t_end);
             double dt;
             (void)choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_next, &dt);
@@ -294,7 +338,29 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 Bb = gb / r.G0;
                 G0b -= gb * ghost / r.G0;
             }
-            if (r.S > 0.0) {
+            if (!fb) {
+                // closure: ln G0 = a0 + s0 y0, ln B = a1 + s1 y1 with y = net(z),
+                // z0 = (S - h0) k0, z2 = (log10 mu2 - h2) k2
+                const double* kc = a.cd.c;
+                const double yb0 = G0b * r.G0 * uniform(kc[kCOutScale]);
+                const double yb1 = Bb * r.B * uniform(kc[kCOutScale + 1]);
+                const double Csat = solubility(p, temperature(q, tm));
+                const double Sbar = (yb0 * cj[0] + yb1 * cj[1]) * uniform(kc[kCInScale]);
+                lamC += Sbar / Csat;
+                const double mbar = (yb0 * cj[2] + yb1 * cj[3]) * uniform(kc[kCInScale + 2]) / (cmu2 * 2.302585092994046);
+                LaneGeom g6 = g;
+                asm volatile("" : "+v"(g6.xb));
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double x = g6.xb + (double)k + 0.5;
+                    const double L = fmax(x, 0.0) * dL;
+                    lam[k] += x > 0.0 ? mbar * (L * L * dL) : 0.0;
+                }
+                if (lane == 0) {
+                    double* rw = rows + (int64_t)(m - 1) * 5;
+                    rw[0] = cz[0]; rw[1] = cz[1]; rw[2] = cz[2]; rw[3] = yb0; rw[4] = yb1;
+                }
+            } else if (r.S > 0.0) {
                 const double Csat = solubility(p, temperature(q, tm));
                 const double dGdS = q.g * r.G0 / r.S;
                 const double dBdS = q.b * r.B / r.S;
@@ -303,6 +369,10 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 gk[1] += G0b * r.G0 * r.lnS;
                 gk[2] += Bb * exp64(q.b * r.lnS) * r.arrB;
                 gk[3] += Bb * r.B * r.lnS;
+            }
+            if (CL != kClosureNone && fb && lane == 0) {
+                double* rw = rows + (int64_t)(m - 1) * 5;
+                rw[0] = 0.0; rw[1] = 0.0; rw[2] = 0.0; rw[3] = 0.0; rw[4] = 0.0;
             }
             lamC = uniform(lamC);
         }
@@ -315,7 +385,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
 }
 
 // Adjoint classes: cells per lane 1-8 and 9-16 (grids up to 1024 cells).
-template <int KLO>
+template <int KLO, int CL>
 __global__ __launch_bounds__(64) void k_adj1d(Adj1dArgs A, int cls_begin, int cls_count, int32_t* queue) {
     // the three SSP-RK3 stage input states of the step being reversed (each lane owns its column)
     __shared__ double lds[3 * (KLO + 7) * 64];
@@ -326,14 +396,14 @@ __global__ __launch_bounds__(64) void k_adj1d(Adj1dArgs A, int cls_begin, int cl
         const int s = uniform(A.fw.order[cls_begin + idx]);
         const int K = uniform((A.fw.ncell[s] + 63) >> 6);
         switch (K - KLO) {
-            case 0: adjoint_sim<KLO + 0>(A, s, lds); break;
-            case 1: adjoint_sim<KLO + 1>(A, s, lds); break;
-            case 2: adjoint_sim<KLO + 2>(A, s, lds); break;
-            case 3: adjoint_sim<KLO + 3>(A, s, lds); break;
-            case 4: adjoint_sim<KLO + 4>(A, s, lds); break;
-            case 5: adjoint_sim<KLO + 5>(A, s, lds); break;
-            case 6: adjoint_sim<KLO + 6>(A, s, lds); break;
-            case 7: adjoint_sim<KLO + 7>(A, s, lds); break;
+            case 0: adjoint_sim<KLO + 0, CL>(A, s, lds); break;
+            case 1: adjoint_sim<KLO + 1, CL>(A, s, lds); break;
+            case 2: adjoint_sim<KLO + 2, CL>(A, s, lds); break;
+            case 3: adjoint_sim<KLO + 3, CL>(A, s, lds); break;
+            case 4: adjoint_sim<KLO + 4, CL>(A, s, lds); break;
+            case 5: adjoint_sim<KLO + 5, CL>(A, s, lds); break;
+            case 6: adjoint_sim<KLO + 6, CL>(A, s, lds); break;
+            case 7: adjoint_sim<KLO + 7, CL>(A, s, lds); break;
             default: break;
         }
     }
@@ -341,23 +411,38 @@ __global__ __launch_bounds__(64) void k_adj1d(Adj1dArgs A, int cls_begin, int cl
 
 }  // namespace
 
-hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
-                              hipStream_t st) {
+template <int CL>
+static hipError_t launch_cl(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
+                            hipStream_t st) {
     if (cls == 0)
-        hipLaunchKernelGGL(k_adj1d<1>, dim3(n_blocks), dim3(64), 0, st, A, begin, count, queue);
+        hipLaunchKernelGGL((k_adj1d<1, CL>), dim3(n_blocks), dim3(64), 0, st, A, begin, count, queue);
     else if (cls == 1)
-        hipLaunchKernelGGL(k_adj1d<9>, dim3(n_blocks), dim3(64), 0, st, A, begin, count, queue);
+        hipLaunchKernelGGL((k_adj1d<9, CL>), dim3(n_blocks), dim3(64), 0, st, A, begin, count, queue);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-int adj1d_class_resident_blocks(int cls) {
+hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
+                              hipStream_t st) {
+    if (A.fw.closure == kClosureBf16) return launch_cl<kClosureBf16>(cls, A, n_blocks, begin, count, queue, st);
+    if (A.fw.closure == kClosureFp64) return launch_cl<kClosureFp64>(cls, A, n_blocks, begin, count, queue, st);
+    return launch_cl<kClosureNone>(cls, A, n_blocks, begin, count, queue, st);
+}
+
+template <int CL>
+static hipError_t adj_occupancy(int cls, int* per_cu) {
+    return cls == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_adj1d<1, CL>, 64, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_adj1d<9, CL>, 64, 0);
+}
+
+int adj1d_class_resident_blocks(int cls, int closure) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e = cls == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj1d<1>, 64, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj1d<9>, 64, 0);
+    const hipError_t e = closure == kClosureBf16   ? adj_occupancy<kClosureBf16>(cls, &per_cu)
+                         : closure == kClosureFp64 ? adj_occupancy<kClosureFp64>(cls, &per_cu)
+                                                   : adj_occupancy<kClosureNone>(cls, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);
 }

@@ -6,6 +6,7 @@
 // fvm1d_device.h for the lane mapping).  Per step: rates from the current
 // concentration, step size, three fused SSP-RK3 stages (or the one-step
 // update), volume moment by wave reduction, solute balance, sampling.
+#include "closure_device.h"
 #include "fvm1d_device.h"
 #include "pbe_internal.h"
 
@@ -14,7 +15,7 @@ namespace {
 
 using namespace dev;
 
-template <int K, int SCHEME>
+template <int K, int SCHEME, int CL>
 __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
     const int lane = threadIdx.x;
     const int N = uniform(a.ncell[s]);
@@ -56,7 +57,20 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
         // keep per-cell geometry from being hoisted out of the time loop into registers
         asm volatile("" : "+v"(g.xb));
         if (step >= a.step_cap) { status |= PBE_SIM_STEPCAP; break; }
-        const Rates r = rates_plain(p, q, C, t);
+        Rates r;
+        if constexpr (CL == kClosureNone) {
+            r = rates_plain(p, q, C, t);
+        } else {
+            // learned closure: inputs S, T and mu_2 of the current state
+            LaneGeom g2 = g;
+            asm volatile("" : "+v"(g2.xb));
+            const double mu2 = wave_sum(lane_moment2(u, g2, dL)) * dL;
+            const ClosureRates cr = closure_rates<false, CL>(a.cd, p, q, C, t, mu2);
+            r.G0 = cr.G0;
+            r.B = cr.B;
+            r.S = cr.S;
+            if (cr.fallback) status |= PBE_SIM_FALLBACK;
+        }
         const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
         double dt;
         const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
@@ -133,7 +147,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
 // One kernel per class of cells-per-lane K (1-8, 9-16, 17-24, 25-32): each
 // class gets the register budget of its largest K instead of the global
 // maximum.  The classes run concurrently, each over its own work queue.
-template <int SCHEME, int KLO>
+template <int SCHEME, int KLO, int CL>
 __global__ __launch_bounds__(64) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cls_count, int32_t* queue) {
     for (;;) {
         // Every lane executes the atomic (only lane 0 adds 1) and the ticket
@@ -147,14 +161,14 @@ __global__ __launch_bounds__(64) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cl
         const int s = uniform(a.order[cls_begin + idx]);
         const int K = uniform((a.ncell[s] + 63) >> 6);
         switch (K - KLO) {
-            case 0: run_sim<KLO + 0, SCHEME>(a, s); break;
-            case 1: run_sim<KLO + 1, SCHEME>(a, s); break;
-            case 2: run_sim<KLO + 2, SCHEME>(a, s); break;
-            case 3: run_sim<KLO + 3, SCHEME>(a, s); break;
-            case 4: run_sim<KLO + 4, SCHEME>(a, s); break;
-            case 5: run_sim<KLO + 5, SCHEME>(a, s); break;
-            case 6: run_sim<KLO + 6, SCHEME>(a, s); break;
-            case 7: run_sim<KLO + 7, SCHEME>(a, s); break;
+            case 0: run_sim<KLO + 0, SCHEME, CL>(a, s); break;
+            case 1: run_sim<KLO + 1, SCHEME, CL>(a, s); break;
+            case 2: run_sim<KLO + 2, SCHEME, CL>(a, s); break;
+            case 3: run_sim<KLO + 3, SCHEME, CL>(a, s); break;
+            case 4: run_sim<KLO + 4, SCHEME, CL>(a, s); break;
+            case 5: run_sim<KLO + 5, SCHEME, CL>(a, s); break;
+            case 6: run_sim<KLO + 6, SCHEME, CL>(a, s); break;
+            case 7: run_sim<KLO + 7, SCHEME, CL>(a, s); break;
             default: break;
         }
     }
@@ -169,17 +183,33 @@ __global__ void k_reset_counter(int32_t* c, int n) {
 template <int SCHEME>
 static hipError_t launch_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* q,
                                hipStream_t st) {
+    constexpr int N = kClosureNone;
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_fvm1d<SCHEME, 1>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        case 1: hipLaunchKernelGGL((k_fvm1d<SCHEME, 9>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        case 2: hipLaunchKernelGGL((k_fvm1d<SCHEME, 17>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        default: hipLaunchKernelGGL((k_fvm1d<SCHEME, 25>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 0: hipLaunchKernelGGL((k_fvm1d<SCHEME, 1, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 1: hipLaunchKernelGGL((k_fvm1d<SCHEME, 9, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 2: hipLaunchKernelGGL((k_fvm1d<SCHEME, 17, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        default: hipLaunchKernelGGL((k_fvm1d<SCHEME, 25, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+    }
+    return hipGetLastError();
+}
+
+// the closure kernels cover SSP-RK3 on grids up to 1024 cells (classes 0 and 1)
+template <int CL>
+static hipError_t launch_closure_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* q,
+                                       hipStream_t st) {
+    constexpr int R = PBE_SCHEME_SSPRK3;
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((k_fvm1d<R, 1, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 1: hipLaunchKernelGGL((k_fvm1d<R, 9, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st) {
+    if (a.closure == kClosureBf16) return launch_closure_class<kClosureBf16>(cls, a, n_blocks, begin, count, queue, st);
+    if (a.closure == kClosureFp64) return launch_closure_class<kClosureFp64>(cls, a, n_blocks, begin, count, queue, st);
     if (a.scheme == PBE_SCHEME_LW_TVD) return launch_class<PBE_SCHEME_LW_TVD>(cls, a, n_blocks, begin, count, queue, st);
     return launch_class<PBE_SCHEME_SSPRK3>(cls, a, n_blocks, begin, count, queue, st);
 }
@@ -189,17 +219,24 @@ hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-int fvm1d_class_resident_blocks(int cls) {
+template <int CL>
+static hipError_t occupancy(int cls, int* per_cu) {
+    constexpr int R = PBE_SCHEME_SSPRK3;
+    switch (cls) {
+        case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 1, CL>, 64, 0);
+        case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 9, CL>, 64, 0);
+        case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 17, kClosureNone>, 64, 0);
+        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 25, kClosureNone>, 64, 0);
+    }
+}
+
+int fvm1d_class_resident_blocks(int cls, int closure) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    switch (cls) {
-        case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fvm1d<PBE_SCHEME_SSPRK3, 1>, 64, 0); break;
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fvm1d<PBE_SCHEME_SSPRK3, 9>, 64, 0); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fvm1d<PBE_SCHEME_SSPRK3, 17>, 64, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fvm1d<PBE_SCHEME_SSPRK3, 25>, 64, 0); break;
-    }
+    const hipError_t e = closure == kClosureBf16   ? occupancy<kClosureBf16>(cls, &per_cu)
+                         : closure == kClosureFp64 ? occupancy<kClosureFp64>(cls, &per_cu)
+                                                   : occupancy<kClosureNone>(cls, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);
 }

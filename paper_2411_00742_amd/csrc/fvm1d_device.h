@@ -301,6 +301,17 @@ __device__ __forceinline__ double lane_moment3(const double (&u)[K], const LaneG
 }
 
 template <int K>
+__device__ __forceinline__ double lane_moment2(const double (&u)[K], const LaneGeom& g, double dL) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double L = fmax(g.xb + (double)k + 0.5, 0.0) * dL;
+        s = fma(L * L, u[k], s);
+    }
+    return s;
+}
+
+template <int K>
 __device__ __forceinline__ void lane_moments(const double (&u)[K], const LaneGeom& g, double dL, double m[4]) {
     m[0] = m[1] = m[2] = m[3] = 0.0;
 #pragma unroll

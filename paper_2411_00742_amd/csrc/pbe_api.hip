@@ -79,6 +79,14 @@ struct pbe_handle {
     double* d_gmom = nullptr;
     double* d_gC = nullptr;
     int adj_blocks[kAdjClasses] = {};
+    // learned closure
+    float* d_blob = nullptr;         // [PBE_MLP_NW + PBE_MLP_NC] current weights and constants
+    void* d_pack = nullptr;          // packed operands (closure_pack_bytes)
+    double* d_tapeR = nullptr;       // [S * ckpt_every * kClosureTape]
+    double* d_rows = nullptr;        // [S * row_cap * 5]
+    double* d_partial = nullptr;     // [n_partial * PBE_MLP_NW]
+    double* d_gmlp = nullptr;        // [PBE_MLP_NW]
+    int row_cap = 0, n_partial = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // 2D
@@ -95,12 +103,28 @@ namespace {
 
 int validate2d(const pbe_problem* p);
 
+// closure blob: finite, positive input scales, a non-empty box, s_min >= 0;
+// the closure kernels run SSP-RK3 on grids of up to 1024 cells
+int validate_closure(const pbe_problem* p) {
+    if (!p->mlp || (p->mlp_precision != PBE_MLP_BF16 && p->mlp_precision != PBE_MLP_FP64)) return PBE_EINVAL;
+    for (int i = 0; i < PBE_MLP_NW + PBE_MLP_NC; ++i)
+        if (!is_finite(p->mlp[i])) return PBE_EINVAL;
+    const float* c = p->mlp + PBE_MLP_NW;
+    for (int k = 0; k < 3; ++k)
+        if (!(c[3 + k] > 0.0f) || !(c[10 + k] <= c[13 + k])) return PBE_EINVAL;
+    if (!(c[16] >= 0.0f)) return PBE_EINVAL;
+    if (p->scheme != PBE_SCHEME_SSPRK3) return PBE_EUNSUPPORTED;
+    for (int s = 0; s < p->n_sims; ++s)
+        if (p->n_cells[s] > kWave * 8 * kAdjClasses) return PBE_EUNSUPPORTED;
+    return PBE_OK;
+}
+
 int validate(const pbe_problem* p) {
     if (!p) return PBE_EINVAL;
     if (p->ndim == 2) return validate2d(p);
     if (p->ndim != 1) return PBE_EINVAL;
     if (p->n_sims < 1 || !p->n_cells || !p->L_max || !p->f0 || !p->C0 || !p->par || !p->t_samples) return PBE_EINVAL;
-    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return p->law == PBE_LAW_MLP ? PBE_EUNSUPPORTED : PBE_EINVAL;
+    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS && p->law != PBE_LAW_MLP) return PBE_EINVAL;
     if (p->scheme != PBE_SCHEME_SSPRK3 && p->scheme != PBE_SCHEME_LW_TVD) return PBE_EINVAL;
     if (p->sol_law != PBE_SOL_LINEAR && p->sol_law != PBE_SOL_EXP) return PBE_EINVAL;
     if (!is_finite(p->cs0) || !is_finite(p->cs1) || !is_finite(p->alpha) || p->alpha < 0.0) return PBE_EINVAL;
@@ -113,6 +137,10 @@ int validate(const pbe_problem* p) {
         if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
     }
     if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
+    if (p->law == PBE_LAW_MLP) {
+        const int rc = validate_closure(p);
+        if (rc != PBE_OK) return rc;
+    }
     if (p->ckpt_every > 0) {
         // the adjoint covers the SSP-RK3 scheme on grids up to 64*16 cells
         if (p->scheme != PBE_SCHEME_SSPRK3) return PBE_EUNSUPPORTED;
@@ -630,6 +658,21 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         h->d_gmom = m.get<double>((size_t)S * ns * 4);
         h->d_gC = m.get<double>((size_t)S * ns);
     }
+    a.closure = kClosureNone;
+    if (p->law == PBE_LAW_MLP) {
+        a.closure = p->mlp_precision == PBE_MLP_FP64 ? kClosureFp64 : kClosureBf16;
+        h->d_blob = m.get<float>(PBE_MLP_NW + PBE_MLP_NC);
+        h->d_pack = m.get<char>(closure_pack_bytes());
+        if (p->ckpt_every > 0) {
+            // one gradient row per (sim, step); rows are read in tiles of 16
+            h->row_cap = (step_cap + 15) / 16 * 16;
+            h->n_partial = 1024;
+            h->d_tapeR = m.get<double>((size_t)S * p->ckpt_every * kClosureTape);
+            h->d_rows = m.get<double>((size_t)S * h->row_cap * 5);
+            h->d_partial = m.get<double>((size_t)h->n_partial * PBE_MLP_NW);
+            h->d_gmlp = m.get<double>(PBE_MLP_NW);
+        }
+    }
     if (!m.ok) return fail(h, PBE_ENOMEM);
     if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -648,9 +691,16 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         hipMemcpy(d_C0, p->C0, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess)
         return fail(h, PBE_EDEVICE);
+    if (a.closure != kClosureNone) {
+        if (hipMemcpy(h->d_blob, p->mlp, sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            pack_closure(h->d_blob, h->d_pack, p->mlp_precision, &a.cd, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return fail(h, PBE_EDEVICE);
+    }
 
     for (int c = 0; c < kFvmClasses; ++c) {
-        const int resident = fvm1d_class_resident_blocks(c);
+        const int resident = fvm1d_class_resident_blocks(c, a.closure);
         if (resident <= 0) return fail(h, PBE_EDEVICE);
         h->cls_blocks[c] = std::max(1, std::min(h->cls_count[c], resident));
         if (c > 0 && hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking) != hipSuccess)
@@ -659,7 +709,7 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     }
     if (p->ckpt_every > 0)
         for (int c = 0; c < kAdjClasses; ++c) {
-            const int resident = adj1d_class_resident_blocks(c);
+            const int resident = adj1d_class_resident_blocks(c, a.closure);
             if (resident <= 0) return fail(h, PBE_EDEVICE);
             h->adj_blocks[c] = std::max(1, std::min(h->cls_count[c], resident));
         }
@@ -785,9 +835,67 @@ int pbe_set_par(pbe_handle* h, const double* par) {
     return PBE_OK;
 }
 
+int pbe_set_mlp(pbe_handle* h, const float* w) {
+    if (!h || !w) return PBE_EINVAL;
+    if (h->two_d || h->a.closure == kClosureNone) return PBE_ESTATE;
+    const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
+    if (!dev)
+        for (int i = 0; i < PBE_MLP_NW; ++i)
+            if (!is_finite(w[i])) return PBE_EINVAL;
+    if (enter(h) != PBE_OK) return PBE_EDEVICE;
+    HIP_OK(hipMemcpyAsync(h->d_blob, w, sizeof(float) * PBE_MLP_NW, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          h->stream));
+    // repack in place: the operand addresses held by the kernels and the graph do not move
+    ClosureDev cd{};
+    HIP_OK(pack_closure(h->d_blob, h->d_pack, h->p.mlp_precision, &cd, h->stream));
+    const int rc = leave(h);
+    if (rc != PBE_OK) return rc;
+    if (!dev) HIP_OK(hipStreamSynchronize(h->stream));
+    h->fresh = true;
+    h->solved = false;
+    return PBE_OK;
+}
+
+int pbe_mlp_forward(const float* blob, int32_t precision, int32_t n, const double* x, double* y, double* dy,
+                    void* hip_stream) {
+    if (!blob || n < 0 || (n > 0 && (!x || !y || !dy))) return PBE_EINVAL;
+    if (precision != PBE_MLP_BF16 && precision != PBE_MLP_FP64) return PBE_EINVAL;
+    for (int i = 0; i < PBE_MLP_NW + PBE_MLP_NC; ++i)
+        if (!is_finite(blob[i])) return PBE_EINVAL;
+    if (!(blob[PBE_MLP_NW + 3] > 0.0f) || !(blob[PBE_MLP_NW + 4] > 0.0f) || !(blob[PBE_MLP_NW + 5] > 0.0f))
+        return PBE_EINVAL;
+    if (n == 0) return PBE_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    Alloc m;
+    float* d_blob = m.get<float>(PBE_MLP_NW + PBE_MLP_NC);
+    char* d_pack = m.get<char>(closure_pack_bytes());
+    if (!m.ok) {
+        m.release();
+        return PBE_ENOMEM;
+    }
+    ClosureDev cd{};
+    int rc = PBE_OK;
+    if (hipMemcpy(d_blob, blob, sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), hipMemcpyHostToDevice) != hipSuccess ||
+        pack_closure(d_blob, d_pack, precision, &cd, st) != hipSuccess ||
+        launch_closure_forward(cd, n, x, y, dy, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        rc = PBE_EDEVICE;
+    m.release();
+    return rc;
+}
+
+int pbe_adam(float* w, float* m, float* v, const double* g, int32_t n, int32_t step, float lr, float beta1,
+             float beta2, float eps, void* hip_stream) {
+    if (!w || !m || !v || !g || n < 0 || step < 1) return PBE_EINVAL;
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return PBE_EINVAL;
+    if (n == 0) return PBE_OK;
+    if (launch_adam(w, m, v, g, n, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+        return PBE_EDEVICE;
+    return PBE_OK;
+}
+
 int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
-             float* gmlp_out) {
-    (void)gmlp_out;
+             double* gmlp_out) {
     if (!h) return PBE_EINVAL;
     if (h->two_d) return PBE_EUNSUPPORTED;
     if (h->p.ckpt_every <= 0 || !h->solved) return PBE_ESTATE;
@@ -816,6 +924,9 @@ int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* 
     A.tape = h->d_tape;
     A.tape_C = h->d_tapeC;
     A.tape_t = h->d_tapeT;
+    A.tape_r = h->d_tapeR;
+    A.rows = h->d_rows;
+    A.row_cap = h->row_cap;
     HIP_OK(hipEventRecord(h->ev_g0, h->stream));
     HIP_OK(launch_reset_counter(h->d_queue, kFvmClasses, h->stream));
     HIP_OK(hipEventRecord(h->ev_fork, h->stream));
@@ -829,9 +940,14 @@ int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* 
             HIP_OK(hipStreamWaitEvent(h->stream, h->ev_join[c], 0));
         }
     }
+    if (h->a.closure != kClosureNone)
+        HIP_OK(launch_closure_grad(h->a.cd, h->d_rows, h->a.step, h->S, h->row_cap, h->d_partial, h->n_partial,
+                                   h->d_gmlp, h->stream));
     HIP_OK(hipEventRecord(h->ev_g1, h->stream));
     h->timed_grad = true;
     int rc = copy_out(h, gpar_out, h->d_gpar, sizeof(double) * (size_t)h->S * PBE_NGRAD);
+    if (rc == PBE_OK && gmlp_out && h->a.closure != kClosureNone)
+        rc = copy_out(h, gmlp_out, h->d_gmlp, sizeof(double) * PBE_MLP_NW);
     if (rc == PBE_OK) rc = leave(h);
     if (rc == PBE_OK && !dev) HIP_OK(hipStreamSynchronize(h->stream));
     return rc;

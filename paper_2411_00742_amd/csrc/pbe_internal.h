@@ -15,6 +15,24 @@ constexpr int kMaxCellsPerLane = 32;  // 1D grids up to 64*32 = 2048 cells per w
 // pointer may sit up to 64*K - N < 2048 cells before a simulation's first cell
 constexpr int kCellGuard = 2048;
 
+// Learned closure operands on the device (packed by pack_closure from the
+// weight blob; layout described in closure_device.h).
+struct ClosureDev {
+    const double* w64;       // fp64 pack: W1[64][3] b1[64] W2T[64][64] (W2T[i][j] = W2[j][i]) b2[64] W3[2][64] b3[2]
+    const uint2* a1;         // layer 1 A operands [4 tiles][64 lanes], 4 bf16 each
+    const uint4* a2;         // layer 2 A operands [4 tiles][2 k-steps][64 lanes], 8 bf16 each
+    const uint4* a3;         // layer 3 A operands [2 k-steps][64 lanes]
+    const uint4* a2t;        // W2 transposed, for the backward [4][2][64]
+    const float* bias;       // b1[64] b2[64] b3[2] pad[2]
+    const float* w3r;        // W3 rounded to bfloat16, as float [2][64]
+    const double* c;         // the 17 constants (normalisation, output scaling, box, s_min)
+    int32_t precision;       // PBE_MLP_BF16 or PBE_MLP_FP64
+    int32_t pad_;
+};
+
+// closure variants of the 1D kernels
+enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2 };
+
 // Everything the 1D forward kernel reads or writes.  Device pointers only.
 struct Fvm1dArgs {
     int32_t n_sims, n_samples;
@@ -51,7 +69,8 @@ struct Fvm1dArgs {
     int32_t max_steps;         // steps allowed in this launch
     int32_t from_initial;      // 1: start from (f0, C0, t = 0)
     int32_t step_cap;          // absolute per-sim step limit (PBE_SIM_STEPCAP when hit)
-    int32_t pad_;
+    int32_t closure;           // kClosure*: which rate law the kernels run
+    ClosureDev cd;             // closure == kClosureBf16 / kClosureFp64
 };
 
 // Adjoint of the 1D solve (reverse sweep over checkpointed segments).
@@ -64,9 +83,13 @@ struct Adj1dArgs {
     double* tape;              // [sum N * ckpt_every] per-sim segment tape of states
     double* tape_C;            // [S * ckpt_every]
     double* tape_t;            // [S * ckpt_every]
+    double* tape_r;            // [S * ckpt_every * kClosureTape] closure quantities of each taped step
+    double* rows;              // [S * row_cap * 5] per-step (z0, z1, z2, ybar0, ybar1) for the weight gradient
+    int32_t row_cap;           // rows per simulation (>= step_cap, multiple of 16)
     int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
-    int32_t pad_;
 };
+// per taped step: fallback flag, G0, B, z0, z1, z2, dy0/dz0, dy1/dz0, dy0/dz2, dy1/dz2, mu2
+constexpr int kClosureTape = 11;
 
 // 2D Godunov-split solver: per global step an L1 row sweep (in place), an L2
 // column march (double buffered) with moment partials, and a per-sim finalize.
@@ -122,16 +145,25 @@ inline int fvm1d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
 hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
 hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st);
-int fvm1d_class_resident_blocks(int cls);
+int fvm1d_class_resident_blocks(int cls, int closure);
 constexpr int kAdjClasses = 2;   // adjoint classes: cells per lane 1-8, 9-16 (grids up to 1024 cells)
 hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
-int adj1d_class_resident_blocks(int cls);
+int adj1d_class_resident_blocks(int cls, int closure);
 constexpr int kRowClasses = 4;   // row sweep classes by cells per lane (rows up to 2048 cells)
 hipError_t launch_rows2d(int cls, const Fvm2dArgs& a, int parity, int begin, int count, hipStream_t st);
 hipError_t launch_cols2d(const Fvm2dArgs& a, int parity, hipStream_t st);
 hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st);
 hipError_t launch_out2d(const Fvm2dArgs& a, double* f_out, hipStream_t st);
+// learned closure (closure.hip)
+constexpr int kMlpWeights = 4546, kMlpConsts = 17;
+size_t closure_pack_bytes();
+hipError_t pack_closure(const float* d_blob, void* mem, int precision, ClosureDev* cd, hipStream_t st);
+hipError_t launch_closure_forward(const ClosureDev& cd, int n, const double* x, double* y, double* dy, hipStream_t st);
+hipError_t launch_closure_grad(const ClosureDev& cd, const double* rows, const int32_t* steps, int n_sims,
+                               int row_cap, double* partial, int n_blocks, double* out, hipStream_t st);
+hipError_t launch_adam(float* w, float* m, float* v, const double* g, int n, int step, float lr, float b1, float b2,
+                       float eps, hipStream_t st);
 
 }  // namespace pbe
 

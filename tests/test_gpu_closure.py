@@ -1,0 +1,182 @@
+"""GPU parity of the learned closure (Sec. 4.2, Fig. 5a) against the oracle.
+
+Tolerances:
+  fp64 network and every fp64 solve: 1e-10 relative, as for the plain law
+    (same arithmetic up to summation order and the exp/log/tanh implementations);
+  bf16 network outputs: |dy| <= 2^-7 (the outputs are logarithms of the rates,
+    so this is a relative bound on G0 and B): both sides round the same values
+    to bfloat16, but the matrix cores accumulate in float32 in their own order,
+    which can move a hidden activation across a bfloat16 rounding boundary
+    (one bfloat16 unit, 2^-8 relative, propagated through a layer of weights
+    of Glorot size); the typical difference is float32 rounding;
+  bf16 tangents (dy/dz): 2^-5 of their scale, since the kernel also rounds
+    the tangent columns to bfloat16 (2^-9 relative per rounding, through
+    three layers) while the oracle carries them exactly;
+  bf16 solves: moments and C within 2^-7 relative (rates bounded as above);
+  bf16 weight gradients: directional derivatives within 2^-3 relative of the
+    oracle's (straight-through derivatives, bfloat16 deltas on the kernel side).
+"""
+import numpy as np
+import pytest
+
+from paper_2411_00742_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+O = W.MLP_OFF
+H = W.MLP_H
+TOL = 1e-10
+
+
+def blob_with_biases(seed=5, gain=0.5):
+    b = W.closure_net(seed_offset=seed, out_gain=gain)
+    b[O["b1"]:O["b1"] + H] = np.linspace(-0.2, 0.25, H)
+    b[O["b2"]:O["b2"] + H] = np.linspace(0.15, -0.1, H)
+    b[O["b3"]:O["b3"] + 2] = [0.3, -0.2]
+    return b
+
+
+def inputs(n, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(0.0, 0.3, n), rng.uniform(15.0, 40.0, n), rng.uniform(13.0, 15.0, n)], axis=1)
+
+
+@pytest.mark.parametrize("prec", [W.MLP_FP64, W.MLP_BF16])
+def test_network_matches_oracle(torch_cuda, oracle, prec):
+    import paper_2411_00742_amd as pbe
+    blob = blob_with_biases()
+    x = inputs(500)
+    y, dy = (t.cpu().numpy() for t in pbe.mlp_forward(blob, prec, x))
+    ry, rdy = oracle.mlp_forward(blob, prec, x, with_jac=True)
+    rdy = rdy[:, :, [0, 2]]
+    if prec == W.MLP_FP64:
+        np.testing.assert_allclose(y, ry, rtol=0, atol=1e-12 * (1 + np.abs(ry)))
+        np.testing.assert_allclose(dy, rdy, rtol=0, atol=1e-12 * np.abs(rdy).max())
+    else:
+        err = np.abs(y - ry)
+        assert err.max() <= 2.0 ** -7, err.max()
+        assert np.median(err) <= 1e-5, np.median(err)
+        assert np.abs(dy - rdy).max() <= 2.0 ** -5 * np.abs(rdy).max()
+
+
+def closure_problem(sizes, t_end=600.0, prec=W.MLP_FP64, blob=None, n_samples=4):
+    prob, _ = W.closure(n_sims=len(sizes), n=200, t_end=t_end, n_samples=n_samples)
+    seeds = [W.gaussian_seed_1d(n, 1000.0, 150.0 + 20.0 * i, 30.0, 1e9) for i, n in enumerate(sizes)]
+    # plain power law for the fallback: the ground truth's kinetics at 30 degC
+    prob.par[:, W.P_KG] = 4e-7
+    prob.par[:, W.P_KB] = 2e9
+    return prob.with_(n_cells=np.array(sizes, dtype=np.int32), f0=np.concatenate(seeds), law=W.LAW_MLP,
+                      mlp=blob_with_biases() if blob is None else blob, mlp_precision=prec)
+
+
+def gpu_solve(prob, **kw):
+    import paper_2411_00742_amd as pbe
+    s = pbe.Solver(prob, **kw)
+    o = {k: v.cpu().numpy() for k, v in s.solve().items()}
+    s.close()
+    return o
+
+
+@pytest.mark.parametrize("prec", [W.MLP_FP64, W.MLP_BF16])
+def test_closure_solve_matches_oracle(torch_cuda, oracle, prec):
+    sizes = [64, 100, 129, 300, 512, 513, 1000, 1024]
+    prob = closure_problem(sizes, prec=prec)
+    o = gpu_solve(prob)
+    offs = prob.offsets()
+    tol = TOL if prec == W.MLP_FP64 else 2.0 ** -7
+    for s in range(prob.n_sims):
+        r = oracle.solve1d(prob, s)
+        assert int(o["status"][s]) == r["status"]
+        if prec == W.MLP_FP64:
+            assert int(o["steps"][s]) == r["steps"]
+            f = o["f"][offs[s]:offs[s + 1]]
+            assert np.abs(f - r["f_final"]).max() <= tol * np.abs(r["f_final"]).max()
+        np.testing.assert_allclose(o["mom"][s], r["mom"], rtol=tol)
+        np.testing.assert_allclose(o["C"][s], r["C"], rtol=tol)
+
+
+def test_fallback_is_the_plain_power_law_bitwise(torch_cuda):
+    blob = blob_with_biases()
+    blob[W.MLP_NW + 16] = 10.0      # s_min above any supersaturation
+    prob = closure_problem([200, 700], blob=blob)
+    a = gpu_solve(prob)
+    b = gpu_solve(prob.with_(law=W.LAW_POWER, mlp=None))
+    assert np.all(a["status"] & 4) and not np.any(b["status"] & 4)
+    for k in ("f", "mom", "C", "steps"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def directions(n, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.normal(size=W.MLP_NW) for _ in range(n)]
+
+
+@pytest.mark.parametrize("prec", [W.MLP_FP64, W.MLP_BF16])
+def test_closure_adjoint_matches_oracle_tangent(torch_cuda, oracle, prec):
+    """Weight gradient (summed over sims) along random directions and the per-sim gamma
+    gradient, against the oracle's forward-mode tangents with the same frozen schedule."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    sizes = [100, 257, 640]
+    prob = closure_problem(sizes, t_end=300.0, prec=prec)
+    prob.par[:, W.P_GAMMA] = [0.0, 5e-4, 1.2e-3]
+    s = pbe.Solver(prob, ckpt_every=16)
+    o = {k: v.cpu().numpy() for k, v in s.solve().items()}
+    rng = np.random.default_rng(3)
+    gmom = rng.normal(size=o["mom"].shape) / np.abs(o["mom"])
+    gC = rng.normal(size=o["C"].shape) / np.abs(o["C"])
+    gpar, gw = s.grad(None, torch.tensor(gmom), torch.tensor(gC), with_mlp=True)
+    gpar, gw = gpar.cpu().numpy(), gw.cpu().numpy()
+    s.close()
+    assert np.all(np.isfinite(gw))
+    vs = directions(3, 7)
+    ref_w = np.zeros(len(vs))
+    for sidx in range(prob.n_sims):
+        for i, v in enumerate(vs):
+            tan = oracle.tangent1d_mlp(prob, sidx, v, with_f=False)
+            d = np.einsum("qk,qk->", gmom[sidx], tan["dM"][..., 0]) + np.einsum("q,q->", gC[sidx], tan["dC"][..., 0])
+            ref_w[i] += d
+            if i == 0:
+                dg = np.einsum("qk,qk->", gmom[sidx], tan["dM"][..., 1]) + np.einsum("q,q->", gC[sidx], tan["dC"][..., 1])
+                if prec == W.MLP_FP64:
+                    assert abs(gpar[sidx, 4] - dg) <= 1e-9 * max(abs(dg), 1e-300), (sidx, gpar[sidx, 4], dg)
+                else:
+                    assert abs(gpar[sidx, 4] - dg) <= 2.0 ** -3 * abs(dg), (sidx, gpar[sidx, 4], dg)
+    got = np.array([gw @ v for v in vs])
+    scale = np.abs(ref_w).max()
+    if prec == W.MLP_FP64:
+        np.testing.assert_allclose(got, ref_w, rtol=1e-9, atol=1e-12 * scale)
+    else:
+        np.testing.assert_allclose(got, ref_w, rtol=2.0 ** -3, atol=2.0 ** -5 * scale)
+
+
+def test_adam_matches_torch(torch_cuda):
+    import torch
+    import paper_2411_00742_amd as pbe
+    rng = np.random.default_rng(0)
+    w0 = rng.normal(size=4546).astype(np.float32)
+    w = torch.tensor(w0, device="cuda")
+    opt = pbe.Adam(w, lr=1e-2)
+    ref = torch.tensor(w0, requires_grad=True)
+    topt = torch.optim.Adam([ref], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    for k in range(5):
+        g = rng.normal(size=4546)
+        opt.step(torch.tensor(g, device="cuda"))
+        ref.grad = torch.tensor(g, dtype=torch.float32)
+        topt.step()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(w.cpu().numpy(), ref.detach().numpy(), rtol=2e-6, atol=2e-7)
+
+
+def test_set_mlp_equals_fresh_handle(torch_cuda):
+    import torch
+    import paper_2411_00742_amd as pbe
+    prob = closure_problem([300, 500], prec=W.MLP_BF16)
+    other = blob_with_biases(seed=11)
+    s = pbe.Solver(prob)
+    s.solve()
+    s.set_mlp(torch.tensor(other[:W.MLP_NW], device="cuda"))
+    a = {k: v.cpu().numpy() for k, v in s.solve().items()}
+    s.close()
+    b = gpu_solve(prob.with_(mlp=other))
+    for k in ("f", "mom", "C", "steps", "status"):
+        assert np.array_equal(a[k], b[k]), k
