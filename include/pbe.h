@@ -54,7 +54,8 @@ enum { PBE_SOL_LINEAR = 0,      /* Csat = cs0 + cs1 T */
 enum { PBE_SIM_OK = 0, PBE_SIM_NONFINITE = 1, PBE_SIM_OUTFLOW = 2, PBE_SIM_FALLBACK = 4 };
 /* pbe_problem.flags */
 enum { PBE_FLAG_DEVICE_PTRS = 1,  /* output/cotangent pointers are device memory, stream-ordered */
-       PBE_FLAG_RECORD_F = 2 };   /* record the number density at every sample time */
+       PBE_FLAG_RECORD_F = 2,     /* record the number density at every sample time */
+       PBE_FLAG_AUTOTUNE = 4 };   /* pick the launch shape with pbe_tune at create (cached per process) */
 
 /* per-sim parameter row */
 enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G2, PBE_P_EG, PBE_P_EB,
@@ -179,6 +180,30 @@ int pbe_adam(float *w, float *m, float *v, const double *g, int32_t n, int32_t s
  * iterations; the handle restarts from the initial condition.  Waits for the
  * handle's queued work first. */
 int pbe_set_par(pbe_handle *h, const double *par);
+
+/* Launch shape chosen by pbe_tune. */
+typedef struct {
+    int32_t blocks[4];          /* 1D: persistent workgroups per kernel class (cells per lane 1-8,
+                                   9-16, 17-24, 25-32; 0 for an empty class) */
+    int32_t seg_2d;             /* 2D: rows per column block of the L2 sweep */
+    int32_t n_candidates;       /* configurations timed; 0 when taken from the process cache */
+    float best_ms;              /* trial time of the chosen configuration */
+    float default_ms;           /* trial time of the default configuration */
+} pbe_tuning;
+
+/* Autotuner: time candidate launch shapes on this handle's own problem and
+ * keep the fastest (1D: persistent grid size per kernel class, as a fraction
+ * 1/4, 1/2, 1, 2 of what fits the device; 2D: column-block length 64, 128,
+ * 256 or 512 rows).  Each candidate runs the solve from the initial
+ * condition, limited to trial_steps steps per simulation (0: to t_end), timed
+ * with HIP events.  1D results do not depend on the launch shape; 2D results
+ * agree to rounding (the moment partial sums are grouped by column block).
+ * The choice is cached per process under the problem's shape (dimension,
+ * sizes, closure variant); with use_cache != 0 a cached choice is applied
+ * without timing.  Blocks; the handle restarts from the initial condition.
+ * out may be NULL.  pbe_create runs this with use_cache = 1 when flags has
+ * PBE_FLAG_AUTOTUNE. */
+int pbe_tune(pbe_handle *h, int32_t trial_steps, int32_t use_cache, pbe_tuning *out);
 
 /* Release all device memory of the handle.  NULL is a no-op. */
 void pbe_destroy(pbe_handle *h);

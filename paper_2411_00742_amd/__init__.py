@@ -19,14 +19,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpbe.so")
 
 PBE_OK, PBE_EINVAL, PBE_ENOMEM, PBE_EDEVICE, PBE_ENONFINITE, PBE_ESTATE, PBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-FLAG_DEVICE_PTRS, FLAG_RECORD_F = 1, 2
+FLAG_DEVICE_PTRS, FLAG_RECORD_F, FLAG_AUTOTUNE = 1, 2, 4
 SIM_OK, SIM_NONFINITE, SIM_OUTFLOW, SIM_FALLBACK, SIM_STEPCAP = 0, 1, 2, 4, 8
 NPAR = 12
 NGRAD = 5
 
 # every entry point of include/pbe.h
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
-           "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_destroy", "pbe_strerror", "pbe_last_kernel_ms"]
+           "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_destroy", "pbe_strerror",
+           "pbe_last_kernel_ms"]
 MLP_NW, MLP_NC = 4546, 17
 MLP_BF16, MLP_FP64 = 0, 1
 
@@ -43,6 +44,11 @@ class PbeProblem(C.Structure):
                 ("dt_max", C.c_double), ("t_end", C.c_double), ("t_samples", _dp),
                 ("ckpt_every", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_int32),
                 ("mlp_precision", C.c_int32)]
+
+
+class PbeTuning(C.Structure):
+    _fields_ = [("blocks", C.c_int32 * 4), ("seg_2d", C.c_int32), ("n_candidates", C.c_int32),
+                ("best_ms", C.c_float), ("default_ms", C.c_float)]
 
 
 class PBEError(RuntimeError):
@@ -72,6 +78,7 @@ def lib():
         L.pbe_set_par.argtypes = [vp, _dp]
         L.pbe_set_mlp.argtypes = [vp, vp]
         L.pbe_mlp_forward.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
+        L.pbe_tune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(PbeTuning)]
         L.pbe_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.pbe_destroy.argtypes = [vp]
         L.pbe_destroy.restype = None
@@ -94,7 +101,7 @@ def _arr(x, dtype):
     return np.ascontiguousarray(x, dtype=dtype)
 
 
-def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, max_steps=0):
+def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, max_steps=0, autotune=False):
     """Build the pbe_problem struct for a workloads.Problem; returns (struct, keepalive)."""
     keep = dict(n_cells=_arr(prob.n_cells.reshape(-1), np.int32), L_max=_arr(prob.L_max.reshape(-1), np.float64),
                 f0=_arr(prob.f0, np.float64), C0=_arr(prob.C0, np.float64), par=_arr(prob.par, np.float64),
@@ -102,7 +109,8 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
     mlp = getattr(prob, "mlp", None)
     if mlp is not None:
         keep["mlp"] = _arr(mlp, np.float32)
-    flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0)
+    flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0) | \
+        (FLAG_AUTOTUNE if autotune else 0)
     st = PbeProblem(ndim=prob.ndim, n_sims=prob.n_sims,
                     n_cells=keep["n_cells"].ctypes.data_as(_ip), L_max=keep["L_max"].ctypes.data_as(_dp),
                     f0=keep["f0"].ctypes.data_as(_dp), C0=keep["C0"].ctypes.data_as(_dp),
@@ -127,7 +135,8 @@ class Solver:
     ordered on torch's current stream.
     """
 
-    def __init__(self, prob, ckpt_every: int = 0, record_f: bool = False, max_steps: int = 0, stream=None):
+    def __init__(self, prob, ckpt_every: int = 0, record_f: bool = False, max_steps: int = 0, stream=None,
+                 autotune: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_2411_00742_amd needs a ROCm GPU; none is visible")
@@ -137,7 +146,7 @@ class Solver:
         self.ckpt_every = ckpt_every
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        st, keep = make_problem_struct(prob, ckpt_every, record_f, True, max_steps)
+        st, keep = make_problem_struct(prob, ckpt_every, record_f, True, max_steps, autotune)
         self._h = C.c_void_p()
         _check(lib().pbe_create(C.byref(st), C.c_void_p(self.stream.cuda_stream), C.byref(self._h)), "pbe_create")
         del keep
@@ -197,6 +206,13 @@ class Solver:
         assert w.numel() == MLP_NW
         _check(lib().pbe_set_mlp(self._h, _ptr(w)), "pbe_set_mlp")
         self._mlp_keep = w
+
+    def tune(self, trial_steps: int = 0, use_cache: bool = False) -> dict:
+        """Run the autotuner (pbe_tune); returns the chosen launch shape and trial times."""
+        t = PbeTuning()
+        _check(lib().pbe_tune(self._h, trial_steps, 1 if use_cache else 0, C.byref(t)), "pbe_tune")
+        return dict(blocks=list(t.blocks), seg_2d=t.seg_2d, n_candidates=t.n_candidates, best_ms=t.best_ms,
+                    default_ms=t.default_ms)
 
     def last_kernel_ms(self):
         a, b = C.c_float(), C.c_float()

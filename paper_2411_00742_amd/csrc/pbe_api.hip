@@ -7,7 +7,10 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <numeric>
 #include <vector>
 
@@ -94,6 +97,10 @@ struct pbe_handle {
     Fvm2dArgs a2{};
     int row_begin[kRowClasses] = {}, row_count[kRowClasses] = {};
     int64_t g2 = 0;                  // global step of the 2D solve (parity selects the buffer)
+    std::vector<int32_t> n1v, n2v;   // 2D grid sizes (host copy, for rebuilding the column blocks)
+    int32_t* d_cb[3] = {};           // 2D column-block tables (sim, col0, row0), sized for the shortest segment
+    int32_t* d_cb_first = nullptr;
+    int resident[kFvmClasses] = {};  // 1D: workgroups of each class that fit the device at once
     std::vector<int32_t> active_host;
     bool fresh = true;               // next pbe_step starts from the initial condition
     bool solved = false;             // a complete pbe_solve with checkpoints exists
@@ -147,7 +154,7 @@ int validate(const pbe_problem* p) {
         for (int s = 0; s < p->n_sims; ++s)
             if (p->n_cells[s] > kWave * 8 * kAdjClasses) return PBE_EUNSUPPORTED;
     }
-    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F)) return PBE_EINVAL;
+    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F | PBE_FLAG_AUTOTUNE)) return PBE_EINVAL;
     int64_t total = 0;
     for (int s = 0; s < p->n_sims; ++s) {
         const int n = p->n_cells[s];
@@ -184,7 +191,7 @@ int validate_common(const pbe_problem* p) {
         if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
     }
     if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
-    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F)) return PBE_EINVAL;
+    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F | PBE_FLAG_AUTOTUNE)) return PBE_EINVAL;
     return PBE_OK;
 }
 
@@ -325,7 +332,8 @@ int write_outputs(pbe_handle* h, double* f_out, double* mom_out, double* C_out, 
 }
 
 // ----------------------------------------------------------------- 2D
-constexpr int k2dSeg = 128;         // rows per L2-sweep block
+constexpr int k2dSeg = 128;         // rows per L2-sweep block (default; pbe_tune may change it)
+constexpr int k2dSegMin = 64;       // shortest segment the column-block tables are sized for
 constexpr int k2dStepsPerGraph = 50;  // global steps captured per graph launch (even)
 
 double step_bound2d(const pbe_problem* p, int s) {
@@ -352,6 +360,35 @@ double step_bound2d(const pbe_problem* p, int s) {
     return p->t_end / dt_min + p->n_samples + 2.0;
 }
 
+// L2-sweep work list for a segment length: blocks of 64 columns x seg rows, sim by sim
+int set_col_blocks(pbe_handle* h, int seg) {
+    const int S = h->S;
+    std::vector<int32_t> cb[3], first(S + 1, 0);
+    for (int s = 0; s < S; ++s) {
+        first[s] = (int)cb[0].size();
+        for (int c0 = 0; c0 < h->n1v[s]; c0 += kWave)
+            for (int r0 = 0; r0 < h->n2v[s]; r0 += seg) {
+                cb[0].push_back(s);
+                cb[1].push_back(c0);
+                cb[2].push_back(r0);
+            }
+    }
+    first[S] = (int)cb[0].size();
+    for (int k = 0; k < 3; ++k)
+        if (hipMemcpy(h->d_cb[k], cb[k].data(), sizeof(int32_t) * cb[k].size(), hipMemcpyHostToDevice) != hipSuccess)
+            return PBE_EDEVICE;
+    if (hipMemcpy(h->d_cb_first, first.data(), sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return PBE_EDEVICE;
+    Fvm2dArgs& a = h->a2;
+    a.cb_sim = h->d_cb[0];
+    a.cb_col0 = h->d_cb[1];
+    a.cb_row0 = h->d_cb[2];
+    a.cb_first = h->d_cb_first;
+    a.n_cb = (int)cb[0].size();
+    a.seg = seg;
+    return PBE_OK;
+}
+
 int create2d(pbe_handle* h, const pbe_problem* p) {
     h->two_d = true;
     const int S = h->S, ns = h->ns;
@@ -376,18 +413,6 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
         }
         h->row_count[c] = (int)row_sim.size() - h->row_begin[c];
     }
-    std::vector<int32_t> cb_sim, cb_col0, cb_row0, cb_first(S + 1, 0);
-    for (int s = 0; s < S; ++s) {
-        cb_first[s] = (int)cb_sim.size();
-        const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
-        for (int c0 = 0; c0 < n1; c0 += kWave)
-            for (int r0 = 0; r0 < n2; r0 += k2dSeg) {
-                cb_sim.push_back(s);
-                cb_col0.push_back(c0);
-                cb_row0.push_back(r0);
-            }
-    }
-    cb_first[S] = (int)cb_sim.size();
     std::vector<int32_t> n1v(S), n2v(S);
     std::vector<double> L1v(S), L2v(S);
     for (int s = 0; s < S; ++s) {
@@ -419,11 +444,12 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
     a.dt = m.get<double>(S); a.hit = m.get<int32_t>(S);
     int32_t* d_row_sim = m.get<int32_t>(row_sim.size());
     int32_t* d_row_j = m.get<int32_t>(row_j.size());
-    int32_t* d_cb_sim = m.get<int32_t>(cb_sim.size());
-    int32_t* d_cb_col0 = m.get<int32_t>(cb_sim.size());
-    int32_t* d_cb_row0 = m.get<int32_t>(cb_sim.size());
-    int32_t* d_cb_first = m.get<int32_t>(S + 1);
-    a.part = m.get<double>(cb_sim.size() * 4);
+    int64_t max_cb = 0;   // column blocks at the shortest segment
+    for (int s = 0; s < S; ++s)
+        max_cb += (int64_t)((n1v[s] + kWave - 1) / kWave) * ((n2v[s] + k2dSegMin - 1) / k2dSegMin);
+    for (int k = 0; k < 3; ++k) h->d_cb[k] = m.get<int32_t>(max_cb);
+    h->d_cb_first = m.get<int32_t>(S + 1);
+    a.part = m.get<double>(max_cb * 4);
     a.mom_s = m.get<double>((size_t)S * ns * 4);
     a.C_s = m.get<double>((size_t)S * ns);
     a.samp_step = m.get<int32_t>((size_t)S * ns);
@@ -431,10 +457,9 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
     a.t_samples = d_ts; a.off = d_off; a.n1 = d_n1; a.n2 = d_n2; a.L1 = d_L1; a.L2 = d_L2; a.par = d_par;
     a.C0 = d_C0; a.f0 = d_f0;
     a.row_sim = d_row_sim; a.row_j = d_row_j;
-    a.cb_sim = d_cb_sim; a.cb_col0 = d_cb_col0; a.cb_row0 = d_cb_row0; a.cb_first = d_cb_first;
-    a.n_cb = (int)cb_sim.size();
-    a.seg = k2dSeg;
     a.step_cap = step_cap;
+    h->n1v = n1v;
+    h->n2v = n2v;
     // the 1D argument block shares the sample buffers so pbe_fetch/pbe_solve copy outputs the same way
     h->a.mom_s = a.mom_s;
     h->a.C_s = a.C_s;
@@ -451,14 +476,10 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
         hipMemcpy(d_C0, p->C0, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_row_sim, row_sim.data(), sizeof(int32_t) * row_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_row_j, row_j.data(), sizeof(int32_t) * row_j.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_cb_sim, cb_sim.data(), sizeof(int32_t) * cb_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_cb_col0, cb_col0.data(), sizeof(int32_t) * cb_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_cb_row0, cb_row0.data(), sizeof(int32_t) * cb_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_cb_first, cb_first.data(), sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(d_row_j, row_j.data(), sizeof(int32_t) * row_j.size(), hipMemcpyHostToDevice) != hipSuccess)
         return PBE_EDEVICE;
     h->active_host.assign(S, 0);
-    return PBE_OK;
+    return set_col_blocks(h, k2dSeg);
 }
 
 // one global step of every active 2D sim
@@ -548,6 +569,128 @@ int write_outputs2d(pbe_handle* h, double* f_out, double* mom_out, double* C_out
 
 }  // namespace
 
+// ----------------------------------------------------------------- autotuner
+// Launch-shape candidates timed on the handle's own problem; the choice is
+// cached per process under the problem's shape signature.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, uint64_t>, pbe_tuning> g_tune_cache;
+
+std::tuple<int, int, int, int, uint64_t> tune_key(const pbe_handle* h) {
+    uint64_t x = 1469598103934665603ull;   // FNV-1a over the grid sizes
+    auto mix = [&](uint64_t v) {
+        x ^= v;
+        x *= 1099511628211ull;
+    };
+    if (h->two_d) {
+        for (int s = 0; s < h->S; ++s) { mix((uint64_t)h->n1v[s]); mix((uint64_t)h->n2v[s]); }
+    } else {
+        for (int s = 0; s < h->S; ++s) mix((uint64_t)h->ncell[s]);
+    }
+    mix((uint64_t)h->p.ckpt_every);
+    mix((uint64_t)h->a.record_f);
+    return std::make_tuple(h->two_d ? 2 : 1, h->S, h->a.closure, h->p.scheme, x);
+}
+
+void drop_graph(pbe_handle* h) {
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+}
+
+int apply_tuning(pbe_handle* h, const pbe_tuning& t) {
+    drop_graph(h);
+    if (h->two_d) return set_col_blocks(h, t.seg_2d);
+    for (int c = 0; c < kFvmClasses; ++c)
+        if (h->cls_count[c] > 0) h->cls_blocks[c] = std::max(1, std::min(h->cls_count[c], t.blocks[c]));
+    return PBE_OK;
+}
+
+// one timed trial of the current launch shape from the initial condition
+int trial_ms(pbe_handle* h, int trial_steps, float* ms) {
+    HIP_OK(hipEventRecord(h->ev_t0, h->stream));
+    if (h->two_d) {
+        int rc = start2d(h);
+        const int n = trial_steps > 0 ? trial_steps : (int)std::min<int64_t>(h->a2.step_cap, 1 << 20);
+        for (int k = 0; k < n && rc == PBE_OK; ++k) rc = step2d_once(h);
+        if (rc != PBE_OK) return rc;
+    } else {
+        int rc = clear_samples(h);
+        if (rc == PBE_OK)
+            rc = launch_classes(h, 1, trial_steps > 0 ? trial_steps : std::numeric_limits<int32_t>::max());
+        if (rc != PBE_OK) return rc;
+    }
+    HIP_OK(hipEventRecord(h->ev_t1, h->stream));
+    HIP_OK(hipEventSynchronize(h->ev_t1));
+    HIP_OK(hipEventElapsedTime(ms, h->ev_t0, h->ev_t1));
+    return PBE_OK;
+}
+
+int tune_handle(pbe_handle* h, int trial_steps, bool use_cache, pbe_tuning* out) {
+    const auto key = tune_key(h);
+    if (use_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            out->n_candidates = 0;
+            const int rc = apply_tuning(h, *out);
+            h->fresh = true;
+            h->solved = false;
+            return rc;
+        }
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    std::vector<pbe_tuning> cands;
+    if (h->two_d) {
+        for (int seg : {k2dSeg, 64, 256, 512}) {
+            pbe_tuning t{};
+            t.seg_2d = seg;
+            cands.push_back(t);
+        }
+    } else {
+        for (double f : {1.0, 0.25, 0.5, 2.0}) {
+            pbe_tuning t{};
+            for (int c = 0; c < kFvmClasses; ++c)
+                t.blocks[c] = h->cls_count[c] > 0
+                                  ? std::max(1, std::min(h->cls_count[c], (int)std::lround(h->resident[c] * f)))
+                                  : 0;
+            cands.push_back(t);
+        }
+    }
+    int best = -1;
+    float best_ms = 0.0f, default_ms = 0.0f;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        int rc = apply_tuning(h, cands[i]);
+        float ms = 0.0f;
+        if (rc == PBE_OK) rc = trial_ms(h, trial_steps, &ms);   // warm-up
+        if (rc == PBE_OK) rc = trial_ms(h, trial_steps, &ms);
+        if (rc != PBE_OK) return rc;
+        if (i == 0) default_ms = ms;
+        if (best < 0 || ms < best_ms) {
+            best = (int)i;
+            best_ms = ms;
+        }
+    }
+    pbe_tuning t = cands[best];
+    t.n_candidates = (int32_t)cands.size();
+    t.best_ms = best_ms;
+    t.default_ms = default_ms;
+    const int rc = apply_tuning(h, t);
+    h->fresh = true;
+    h->solved = false;
+    h->timed_solve = false;
+    if (rc != PBE_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = t;
+    }
+    *out = t;
+    return PBE_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* pbe_strerror(int code) {
@@ -582,8 +725,13 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
             hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) != hipSuccess ||
             hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess)
             return fail(h, PBE_EDEVICE);
-        const int rc = create2d(h, p);
+        int rc = create2d(h, p);
         if (rc != PBE_OK) return fail(h, rc);
+        if (p->flags & PBE_FLAG_AUTOTUNE) {
+            pbe_tuning t{};
+            rc = tune_handle(h, 40, true, &t);
+            if (rc != PBE_OK) return fail(h, rc);
+        }
         *out = h;
         return PBE_OK;
     }
@@ -702,6 +850,7 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     for (int c = 0; c < kFvmClasses; ++c) {
         const int resident = fvm1d_class_resident_blocks(c, a.closure);
         if (resident <= 0) return fail(h, PBE_EDEVICE);
+        h->resident[c] = resident;
         h->cls_blocks[c] = std::max(1, std::min(h->cls_count[c], resident));
         if (c > 0 && hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking) != hipSuccess)
             return fail(h, PBE_EDEVICE);
@@ -717,6 +866,11 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         hipEventCreate(&h->ev_t0) != hipSuccess || hipEventCreate(&h->ev_t1) != hipSuccess ||
         hipEventCreate(&h->ev_g0) != hipSuccess || hipEventCreate(&h->ev_g1) != hipSuccess)
         return fail(h, PBE_EDEVICE);
+    if (p->flags & PBE_FLAG_AUTOTUNE) {
+        pbe_tuning t{};
+        const int rc = tune_handle(h, 0, true, &t);
+        if (rc != PBE_OK) return fail(h, rc);
+    }
     *out = h;
     return PBE_OK;
 }
@@ -970,6 +1124,14 @@ int pbe_last_kernel_ms(pbe_handle* h, float* solve_ms, float* grad_ms) {
         }
     }
     return PBE_OK;
+}
+
+int pbe_tune(pbe_handle* h, int32_t trial_steps, int32_t use_cache, pbe_tuning* out) {
+    if (!h || trial_steps < 0) return PBE_EINVAL;
+    pbe_tuning t{};
+    int rc = tune_handle(h, trial_steps, use_cache != 0, &t);
+    if (rc == PBE_OK && out) *out = t;
+    return rc;
 }
 
 void pbe_destroy(pbe_handle* h) {
