@@ -111,6 +111,58 @@ def gradient_leg(steps: int):
                 cell_steps_per_solve=cell_steps, finite=finite)
 
 
+def closure_leg(steps: int):
+    """Learned-closure workload: 4096 sims x 500 cells with the bf16 MFMA closure in place of the
+    rate laws.  Reports forward cell-updates/s and the time of one training iteration
+    (forward with checkpoints, adjoint, weight gradient over all steps, Adam, repack)."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    from paper_2411_00742_amd import workloads as W
+    truth, _ = W.closure()
+    par = truth.par.copy()
+    par[:, W.P_KG] = 4e-7
+    par[:, W.P_KB] = 2e9
+    prob = truth.with_(law=W.LAW_MLP, par=par, mlp=W.closure_net(), mlp_precision=W.MLP_BF16)
+    fw = pbe.Solver(prob)
+    out = fw.solve()
+    torch.cuda.synchronize()
+    st = out["steps"].cpu().numpy().astype(np.int64)
+    cu = int((st * prob.n_cells.astype(np.int64)).sum())
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fw.solve(out)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    fw.close()
+    tr = pbe.Solver(prob, ckpt_every=32)
+    w = torch.tensor(prob.mlp[:W.MLP_NW], device="cuda")
+    opt = pbe.Adam(w, lr=1e-3)
+    o = tr.solve()
+    gmom = torch.randn_like(o["mom"]) / o["mom"].abs()
+    gC = torch.randn_like(o["C"]) / o["C"].abs()
+
+    def iteration():
+        tr.solve(o)
+        _, gw = tr.grad(None, gmom, gC, with_mlp=True)
+        opt.step(gw)
+        tr.set_mlp(w)
+        return gw
+
+    iteration()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gw = iteration()
+    torch.cuda.synchronize()
+    it = (time.perf_counter() - t0) / steps
+    finite = bool(torch.isfinite(gw).all().item())
+    tr.close()
+    rows = int(st.sum())
+    return dict(value=cu / el, unit="cell-updates/s (bf16 MFMA closure)", n_sims=prob.n_sims, cells=500,
+                ms_per_solve=1e3 * el, training_iteration_ms=1e3 * it, gradient_rows=rows,
+                closure_evals_per_s=rows / el, finite=finite)
+
+
 def fvm2d_leg(steps: int):
     """2D length x width workload: 64 sims on n x n grids, n ~ U{256..1024}, Lie-split SSP-RK3."""
     import torch
@@ -143,6 +195,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint-gradient leg")
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D leg")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--steps-closure", type=int, default=3)
     ap.add_argument("--steps-2d", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -158,7 +212,9 @@ def main():
     dev = torch.cuda.get_device_name(0)
     prob = W.batched()
     log(f"[bench] {dev}: {prob.name}, {int(prob.n_cells.sum())} cells")
-    solver = pbe.Solver(prob)
+    solver = pbe.Solver(prob, autotune=True)
+    tuning = solver.tune(use_cache=True)
+    log(f"[bench] launch shape {tuning}")
     out = solver.solve()
     torch.cuda.synchronize()
     steps = out["steps"].cpu().numpy().astype(np.int64)
@@ -219,10 +275,15 @@ def main():
                              "batched_speedup": value / plain},
         "roofline": roofline,
         "kernel_ms": avg_kernel_ms,
+        "launch_shape": {"blocks_per_class": tuning["blocks"], "tuned_ms": tuning["best_ms"],
+                         "default_ms": tuning["default_ms"]},
     }
     if not args.no_grad:
         result["gradient"] = gradient_leg(args.grad_steps)
         log(f"[bench] gradient leg: {result['gradient']}")
+    if not args.no_closure:
+        result["closure"] = closure_leg(args.steps_closure)
+        log(f"[bench] closure leg: {result['closure']}")
     if not args.no_2d:
         result["fvm2d"] = fvm2d_leg(args.steps_2d)
         log(f"[bench] 2D leg: {result['fvm2d']}")

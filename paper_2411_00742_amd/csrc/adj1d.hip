@@ -56,7 +56,7 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
         const double p = a * b;
         const bool same = p > 0.0;
         const double s = same ? a + b : 1.0;
-        const double r = 1.0 / s;
+        const double r = recip_limiter(s);   // the forward's reciprocal, so psi matches it bitwise
         const double psi = same ? (p + p) * r : 0.0;
         // d psi/da = 2 (b/(a+b))^2, d psi/db = 2 (a/(a+b))^2: both ratios lie in (0, 1]
         // when ab > 0, so neither factor over- or underflows in the far tails of f
