@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D leg")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch shape first (pbe_tune)")
     ap.add_argument("--steps-closure", type=int, default=3)
     ap.add_argument("--steps-2d", type=int, default=2)
     args = ap.parse_args()
@@ -212,8 +213,8 @@ def main():
     dev = torch.cuda.get_device_name(0)
     prob = W.batched()
     log(f"[bench] {dev}: {prob.name}, {int(prob.n_cells.sum())} cells")
-    solver = pbe.Solver(prob, autotune=True)
-    tuning = solver.tune(use_cache=True)
+    solver = pbe.Solver(prob, autotune=args.tune)
+    tuning = solver.tune(use_cache=True) if args.tune else dict(blocks=None, best_ms=None, default_ms=None)
     log(f"[bench] launch shape {tuning}")
     out = solver.solve()
     torch.cuda.synchronize()
@@ -239,7 +240,7 @@ def main():
         f"{value:.4e} cell-updates/s")
 
     # plain path: the same kind of simulations, one per launch
-    pick = np.linspace(0, prob.n_sims - 1, args.plain_sims).astype(int)
+    pick = np.linspace(0, prob.n_sims - 1, max(args.plain_sims, 1)).astype(int)
     plain_cells, plain_s = 0, 0.0
     for s in pick:
         one = pbe.Solver(prob.subset([s]))

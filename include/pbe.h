@@ -186,6 +186,8 @@ typedef struct {
     int32_t blocks[4];          /* 1D: persistent workgroups per kernel class (cells per lane 1-8,
                                    9-16, 17-24, 25-32; 0 for an empty class) */
     int32_t seg_2d;             /* 2D: rows per column block of the L2 sweep */
+    int32_t pair_long;          /* 1D: grids over 1024 cells run on wave pairs (class 2) instead of
+                                   one wavefront with 17-32 cells per lane (classes 2, 3) */
     int32_t n_candidates;       /* configurations timed; 0 when taken from the process cache */
     float best_ms;              /* trial time of the chosen configuration */
     float default_ms;           /* trial time of the default configuration */
@@ -193,8 +195,9 @@ typedef struct {
 
 /* Autotuner: time candidate launch shapes on this handle's own problem and
  * keep the fastest (1D: persistent grid size per kernel class, as a fraction
- * 1/4, 1/2, 1, 2 of what fits the device; 2D: column-block length 64, 128,
- * 256 or 512 rows).  Each candidate runs the solve from the initial
+ * 1/4, 1/2, 1, 2 of what fits the device, one wavefront per simulation; 2D:
+ * column-block length 64, 128, 256 or 512 rows).  Wave pairs for grids over
+ * 1024 cells are selected with pbe_set_launch.  Each candidate runs the solve from the initial
  * condition, limited to trial_steps steps per simulation (0: to t_end), timed
  * with HIP events.  1D results do not depend on the launch shape; 2D results
  * agree to rounding (the moment partial sums are grouped by column block).
@@ -204,6 +207,14 @@ typedef struct {
  * out may be NULL.  pbe_create runs this with use_cache = 1 when flags has
  * PBE_FLAG_AUTOTUNE. */
 int pbe_tune(pbe_handle *h, int32_t trial_steps, int32_t use_cache, pbe_tuning *out);
+
+/* Apply a launch shape without timing (e.g. one pbe_tune chose before): the
+ * fields of pbe_tuning that describe the shape are used (blocks and
+ * pair_long for 1D, seg_2d for 2D; seg_2d in [16, 4096]); counts are clipped to
+ * each class's size.  pair_long requires the plain rate laws.  The handle
+ * restarts from the initial condition.  PBE_EINVAL on a NULL or out-of-range
+ * argument. */
+int pbe_set_launch(pbe_handle *h, const pbe_tuning *t);
 
 /* Release all device memory of the handle.  NULL is a no-op. */
 void pbe_destroy(pbe_handle *h);

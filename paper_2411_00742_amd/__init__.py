@@ -26,7 +26,7 @@ NGRAD = 5
 
 # every entry point of include/pbe.h
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
-           "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_destroy", "pbe_strerror",
+           "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_set_launch", "pbe_destroy", "pbe_strerror",
            "pbe_last_kernel_ms"]
 MLP_NW, MLP_NC = 4546, 17
 MLP_BF16, MLP_FP64 = 0, 1
@@ -47,7 +47,7 @@ class PbeProblem(C.Structure):
 
 
 class PbeTuning(C.Structure):
-    _fields_ = [("blocks", C.c_int32 * 4), ("seg_2d", C.c_int32), ("n_candidates", C.c_int32),
+    _fields_ = [("blocks", C.c_int32 * 4), ("seg_2d", C.c_int32), ("pair_long", C.c_int32), ("n_candidates", C.c_int32),
                 ("best_ms", C.c_float), ("default_ms", C.c_float)]
 
 
@@ -79,6 +79,7 @@ def lib():
         L.pbe_set_mlp.argtypes = [vp, vp]
         L.pbe_mlp_forward.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.pbe_tune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(PbeTuning)]
+        L.pbe_set_launch.argtypes = [vp, C.POINTER(PbeTuning)]
         L.pbe_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.pbe_destroy.argtypes = [vp]
         L.pbe_destroy.restype = None
@@ -211,8 +212,18 @@ class Solver:
         """Run the autotuner (pbe_tune); returns the chosen launch shape and trial times."""
         t = PbeTuning()
         _check(lib().pbe_tune(self._h, trial_steps, 1 if use_cache else 0, C.byref(t)), "pbe_tune")
-        return dict(blocks=list(t.blocks), seg_2d=t.seg_2d, n_candidates=t.n_candidates, best_ms=t.best_ms,
+        return dict(blocks=list(t.blocks), seg_2d=t.seg_2d, pair_long=t.pair_long, n_candidates=t.n_candidates,
+                    best_ms=t.best_ms,
                     default_ms=t.default_ms)
+
+    def set_launch(self, blocks=(0, 0, 0, 0), seg_2d: int = 128, pair_long: bool = False):
+        """Apply a launch shape (pbe_set_launch); 0 blocks means what fits the device."""
+        t = PbeTuning()
+        for i, b in enumerate(blocks):
+            t.blocks[i] = int(b)
+        t.seg_2d = seg_2d
+        t.pair_long = 1 if pair_long else 0
+        _check(lib().pbe_set_launch(self._h, C.byref(t)), "pbe_set_launch")
 
     def last_kernel_ms(self):
         a, b = C.c_float(), C.c_float()

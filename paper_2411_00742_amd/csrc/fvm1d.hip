@@ -15,9 +15,12 @@ namespace {
 
 using namespace dev;
 
-template <int K, int SCHEME, int CL>
-__device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
-    const int lane = threadIdx.x;
+// W = 1: one wavefront per simulation; W = 2: a wave pair (see Pair), with
+// `lane` the global lane 0..127 of the right-aligned layout.
+template <int K, int SCHEME, int CL, int W>
+__device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
+    static_assert(W == 1 || CL == kClosureNone, "the closure kernels run one wavefront per simulation");
+    const int lane = W == 2 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     const int N = uniform(a.ncell[s]);
     const int64_t base = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
     const double Lmax = uniform(a.Lmax[s]);
@@ -27,7 +30,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
     const int ns = a.n_samples;
     const double* ts = a.t_samples;
 
-    const int pad = 64 * K - N;
+    const int pad = 64 * W * K - N;
     LaneGeom g;
     g.xb = (double)(lane * K - pad);
     g.gdL = q.gamma * dL;
@@ -42,7 +45,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
     if (a.from_initial) {
         C = uniform(a.C0[s]);
         t = 0.0;
-        mu3_old = wave_sum(lane_moment3(u, g, dL)) * dL;
+        mu3_old = group_sum<W>(wave_sum(lane_moment3(u, g, dL)), pr) * dL;
         out = 0.0;
         step = 0; next = 0; status = 0;
     } else {
@@ -93,13 +96,13 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
         }
 
         const double cour = dt * r.G0 / dL;
-        const double hN = fvm_step<K, SCHEME>(u, g, cour, ghost);
+        const double hN = fvm_step<K, SCHEME, W>(u, g, cour, ghost, pr);
         out = fma(dt * r.G0, hN, out);
 
         // discrete solute balance, Eq. (9): C^{n+1} = C^n - alpha (mu3^{n+1} - mu3^n)
         LaneGeom gm = g;
         asm volatile("" : "+v"(gm.xb));
-        const double mu3 = wave_sum(lane_moment3(u, gm, dL)) * dL;
+        const double mu3 = group_sum<W>(wave_sum(lane_moment3(u, gm, dL)), pr) * dL;
         C = uniform(C - p.alpha * (mu3 - mu3_old));
         mu3_old = mu3;
         t = uniform(hit ? t_next : t + dt);
@@ -116,7 +119,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
                 lane_moments(u, gm, dL, m);
                 const int64_t o = (int64_t)s * ns + next;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) m[j] = wave_sum(m[j]) * dL;
+                for (int j = 0; j < 4; ++j) m[j] = group_sum<W>(wave_sum(m[j]), pr) * dL;
                 if (lane == 0) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) a.mom_s[o * 4 + j] = m[j];
@@ -131,24 +134,34 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s) {
 
     // save the running state
     store_cells(u, a.f + base, i0, g.npad);
+    // the outflow face belongs to lane 63 of the last wave, which writes the per-sim scalars
     const double out63 = lane_value(out, 63);
     if (!(t < p.t_end) || (status & PBE_SIM_NONFINITE)) {
         double m[4];
         lane_moments(u, g, dL, m);
-        const double mu0 = wave_sum(m[0]) * dL;
+        const double mu0 = group_sum<W>(wave_sum(m[0]), pr) * dL;
         if (out63 > 1e-12 * fmax(mu0, 1e-300)) status |= PBE_SIM_OUTFLOW;
     }
-    if (lane == 0) {
+    if (lane == 64 * (W - 1)) {
         a.C[s] = C; a.t[s] = t; a.mu3[s] = mu3_old; a.outflow[s] = out63;
         a.step[s] = step; a.next[s] = next; a.status[s] = status;
     }
 }
 
-// One kernel per class of cells-per-lane K (1-8, 9-16, 17-24, 25-32): each
-// class gets the register budget of its largest K instead of the global
-// maximum.  The classes run concurrently, each over its own work queue.
+// One kernel per class of cells-per-lane K (1-8, 9-16; longer grids use the
+// wave-pair kernel below): each class gets the register budget of its largest
+// K instead of the global maximum.  The classes run concurrently, each over
+// its own work queue.
+// waves per SIMD each class is held to (the register budget follows: 4 -> 128,
+// 3 -> 168, 2 -> 256 VGPRs); the 25-32 class needs the whole budget, and the
+// closure's network takes one step of occupancy more
+constexpr int fvm_waves_per_simd(int klo, int cl) {
+    return cl != 0 ? (klo == 1 ? 3 : 2) : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
+}
+
 template <int SCHEME, int KLO, int CL>
-__global__ __launch_bounds__(64) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cls_count, int32_t* queue) {
+__global__ __launch_bounds__(64, fvm_waves_per_simd(KLO, CL)) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cls_count,
+                                                                        int32_t* queue) {
     for (;;) {
         // Every lane executes the atomic (only lane 0 adds 1) and the ticket
         // is lane 0's return value.  Popping inside `if (lane == 0)` instead
@@ -161,14 +174,52 @@ __global__ __launch_bounds__(64) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cl
         const int s = uniform(a.order[cls_begin + idx]);
         const int K = uniform((a.ncell[s] + 63) >> 6);
         switch (K - KLO) {
-            case 0: run_sim<KLO + 0, SCHEME, CL>(a, s); break;
-            case 1: run_sim<KLO + 1, SCHEME, CL>(a, s); break;
-            case 2: run_sim<KLO + 2, SCHEME, CL>(a, s); break;
-            case 3: run_sim<KLO + 3, SCHEME, CL>(a, s); break;
-            case 4: run_sim<KLO + 4, SCHEME, CL>(a, s); break;
-            case 5: run_sim<KLO + 5, SCHEME, CL>(a, s); break;
-            case 6: run_sim<KLO + 6, SCHEME, CL>(a, s); break;
-            case 7: run_sim<KLO + 7, SCHEME, CL>(a, s); break;
+            case 0: run_sim<KLO + 0, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 1: run_sim<KLO + 1, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 2: run_sim<KLO + 2, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 3: run_sim<KLO + 3, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 4: run_sim<KLO + 4, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 5: run_sim<KLO + 5, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 6: run_sim<KLO + 6, SCHEME, CL, 1>(a, s, nullptr); break;
+            case 7: run_sim<KLO + 7, SCHEME, CL, 1>(a, s, nullptr); break;
+            default: break;
+        }
+    }
+}
+
+// Grids of more than 1024 cells on a wave pair: K = ceil(N/128) = 9..16 cells
+// per lane, so a long simulation gets the register budget (and occupancy) of
+// the 513-1024-cell class and half the serial work per wave, at the price of
+// the per-step scalar work done twice and a barrier per stage.  This wins when
+// there are too few simulations to fill the device; with thousands of
+// simulations one wave per simulation is faster.  The autotuner chooses.
+template <int SCHEME>
+__global__ __launch_bounds__(128) void k_fvm1d_pair(Fvm1dArgs a, int cls_begin, int cls_count, int32_t* queue) {
+    __shared__ double xs[kPairSlots];
+    __shared__ int ticket_slot;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    Pair pr{xs, w, 0};
+    for (;;) {
+        // wave 0 takes the ticket (branch-free within the wave, as in k_fvm1d)
+        if (w == 0) {
+            const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
+            ticket_slot = __builtin_amdgcn_readfirstlane(ticket);
+        }
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(ticket_slot);
+        __syncthreads();   // the slot is rewritten only after both waves have read it
+        if (idx >= cls_count) break;
+        const int s = uniform(a.order[cls_begin + idx]);
+        const int K = uniform((a.ncell[s] + 127) >> 7);
+        switch (K - 9) {
+            case 0: run_sim<9, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 1: run_sim<10, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 2: run_sim<11, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 3: run_sim<12, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 4: run_sim<13, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 5: run_sim<14, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 6: run_sim<15, SCHEME, kClosureNone, 2>(a, s, &pr); break;
+            case 7: run_sim<16, SCHEME, kClosureNone, 2>(a, s, &pr); break;
             default: break;
         }
     }
@@ -187,7 +238,12 @@ static hipError_t launch_class(int cls, const Fvm1dArgs& a, int n_blocks, int be
     switch (cls) {
         case 0: hipLaunchKernelGGL((k_fvm1d<SCHEME, 1, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
         case 1: hipLaunchKernelGGL((k_fvm1d<SCHEME, 9, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        case 2: hipLaunchKernelGGL((k_fvm1d<SCHEME, 17, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 2:
+            if (a.pair_long)
+                hipLaunchKernelGGL((k_fvm1d_pair<SCHEME>), dim3(n_blocks), dim3(128), 0, st, a, begin, count, q);
+            else
+                hipLaunchKernelGGL((k_fvm1d<SCHEME, 17, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
+            break;
         default: hipLaunchKernelGGL((k_fvm1d<SCHEME, 25, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
     }
     return hipGetLastError();
@@ -220,23 +276,25 @@ hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st) {
 }
 
 template <int CL>
-static hipError_t occupancy(int cls, int* per_cu) {
+static hipError_t occupancy(int cls, int pairs, int* per_cu) {
     constexpr int R = PBE_SCHEME_SSPRK3;
     switch (cls) {
         case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 1, CL>, 64, 0);
         case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 9, CL>, 64, 0);
-        case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 17, kClosureNone>, 64, 0);
+        case 2:
+            if (pairs) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d_pair<R>, 128, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 17, kClosureNone>, 64, 0);
         default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 25, kClosureNone>, 64, 0);
     }
 }
 
-int fvm1d_class_resident_blocks(int cls, int closure) {
+int fvm1d_class_resident_blocks(int cls, int closure, int pairs) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const hipError_t e = closure == kClosureBf16   ? occupancy<kClosureBf16>(cls, &per_cu)
-                         : closure == kClosureFp64 ? occupancy<kClosureFp64>(cls, &per_cu)
-                                                   : occupancy<kClosureNone>(cls, &per_cu);
+    const hipError_t e = closure == kClosureBf16   ? occupancy<kClosureBf16>(cls, pairs, &per_cu)
+                         : closure == kClosureFp64 ? occupancy<kClosureFp64>(cls, pairs, &per_cu)
+                                                   : occupancy<kClosureNone>(cls, pairs, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);
 }

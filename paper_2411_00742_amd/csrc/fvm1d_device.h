@@ -72,6 +72,42 @@ __device__ __forceinline__ double wave_sum(double v) {
     return lane_value(v, 63);
 }
 
+// ---------------------------------------------------------------- wave pairs
+// Long simulations run on two wavefronts of one workgroup: wave w holds the
+// global lanes 64w..64w+63 of the right-aligned layout.  The two values that
+// cross the wave boundary in each stage, and the per-step sums, pass through
+// a few LDS slots around a workgroup barrier.  Every branch of the time loop
+// depends only on values both waves hold bitwise identically (t, C, step,
+// status, and sums combined in the same order), so both waves always reach
+// the same barriers.
+struct Pair {
+    double* x;   // workgroup LDS: two alternating sets of 6 slots, then a write sink of 128 doubles
+    int w;       // this wave's index in the workgroup
+    int ph;      // which slot set the next exchange uses (both waves flip it in step)
+};
+constexpr int kPairSlots = 12 + 128;
+
+// lane `mine` stores v in slot k; every other lane writes its own sink slot (no branch)
+__device__ __forceinline__ void publish(const Pair& pr, int slot, bool mine, double v) {
+    pr.x[mine ? slot : 12 + (int)threadIdx.x] = v;
+}
+
+// Sum of a wave-uniform value over the simulation's waves, identical on all of
+// them.  One barrier: the slot set alternates, so a wave can only overwrite a
+// set after the other wave has passed the next barrier, i.e. has read it.
+template <int W>
+__device__ __forceinline__ double group_sum(double wave_total, Pair* pr) {
+    if constexpr (W == 1) {
+        return wave_total;
+    } else {
+        double* x = pr->x + 6 * pr->ph;
+        pr->ph ^= 1;
+        x[4 + pr->w] = wave_total;   // all lanes of the wave store the same value
+        __syncthreads();
+        return uniform(x[4] + x[5]);
+    }
+}
+
 // ---------------------------------------------------------------- process
 struct Process {
     int law, scheme, sol_law;
@@ -173,7 +209,7 @@ __device__ __forceinline__ bool choose_dt(const Process& p, double G0, double ga
 // van Leer limited slope psi = phi(a/b)*b = 2ab/(a+b) when a and b share a
 // strict sign, else 0 (SI Eqs. (S1)-(S2) in division-safe form).
 // 1/d for the limiter's denominator d = a + b with ab > 0 (so |d| >= 2 sqrt(ab)
-// >= 4.4e-162, never subnormal, and 1/d stays finite), or d = 1: hardware
+// >= 4.4e-162, never subnormal, and 1/d stays finite): hardware
 // reciprocal refined by two Newton steps (within an ulp or so of 1/d), six
 // VALU operations instead of the eleven of the correctly rounded division.
 __device__ __forceinline__ double recip_limiter(double d) {
@@ -187,8 +223,10 @@ __device__ __forceinline__ double recip_limiter(double d) {
 __device__ __forceinline__ double limited_slope(double a, double b) {
     const double p = a * b;
     const bool same = p > 0.0;
-    // branch-free: 0 times 1/1 where the slopes disagree
-    return (same ? p + p : 0.0) * recip_limiter(same ? a + b : 1.0);
+    // one select at the end: where the slopes disagree a + b may be 0 or tiny and
+    // the quotient garbage, but it is discarded
+    const double q = (p + p) * recip_limiter(a + b);
+    return same ? q : 0.0;
 }
 
 // Face value H = w (f_i + kappa/2 psi) with w = G(L_face)/G0; the face flux is
@@ -218,16 +256,44 @@ __device__ __forceinline__ double face_weight(const LaneGeom& g, int k) {
 // One Runge-Kutta stage on the wavefront's cells:
 //   v = u + c (H_{i-1/2} - H_{i+1/2}),   u <- first ? v : wa*u0 + wb*v
 // with c = dt*G0/dL.  Returns this lane's last face value (lane 63: L_max).
-template <int K, int SCHEME>
+template <int K, int SCHEME, int W = 1>
 __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K], LaneGeom g, double c,
-                                            double ghost, double wa, double wb, bool first) {
+                                            double ghost, double wa, double wb, bool first, Pair* pr = nullptr) {
+    static_assert(W == 1 || K >= 2, "wave pairs hold at least two cells per lane");
     // recompute the face weights in every stage instead of keeping K of them live
     asm volatile("" : "+v"(g.xb));
-    const double uL = shift_from_left(u[K - 1], ghost);
-    const double uR = shift_from_right(u[0], 0.0);
+    // values entering at the wave's ends: the inflow ghost on the left and 0
+    // beyond L_max, or the neighbouring wave's boundary cells
+    double fillL = ghost, fillR = 0.0;
+    double b_um1 = 0.0, b_ui = 0.0, b_up1 = 0.0;
+    if constexpr (W == 2) {
+        const int lane = threadIdx.x & 63;
+        const int set = 6 * pr->ph;   // alternate slot sets: see group_sum
+        pr->ph ^= 1;
+        publish(*pr, set + 0, pr->w == 0 && lane == 63, u[K - 1]);
+        publish(*pr, set + 1, pr->w == 0 && lane == 63, u[K >= 2 ? K - 2 : 0]);
+        publish(*pr, set + 2, pr->w == 1 && lane == 0, u[0]);
+        __syncthreads();
+        b_ui = pr->x[set + 0];
+        b_um1 = pr->x[set + 1];
+        b_up1 = pr->x[set + 2];
+        fillL = pr->w == 1 ? b_ui : ghost;
+        fillR = pr->w == 0 ? b_up1 : 0.0;
+    }
+    const double uL = shift_from_left(u[K - 1], fillL);
+    const double uR = shift_from_right(u[0], fillR);
     const double Hlast = face_value<SCHEME>(K >= 2 ? u[K >= 2 ? K - 2 : 0] : uL, u[K - 1], uR,
                                             face_weight(g, K - 1), c);
-    const double HL = shift_from_left(Hlast, ghost);
+    double fillH = ghost;
+    if constexpr (W == 2) {
+        // wave 1 forms the face between the waves from the same three cells, the
+        // same face coordinate and the same code as lane 63 of wave 0, so both
+        // waves hold that face value bitwise; no second exchange is needed
+        const double xf = lane_value(g.xb, 0);   // slot-0 cell index of lane 0 = index of that face
+        const double Hb = face_value<SCHEME>(b_um1, b_ui, b_up1, fma(g.gdL, fmax(xf, 0.0), 1.0), c);
+        fillH = pr->w == 1 ? Hb : ghost;
+    }
+    const double HL = shift_from_left(Hlast, fillH);
     double Hprev = HL, um1 = uL;
     double ui = u[0];
     double xk = g.xb;   // cell index of slot k
@@ -255,20 +321,21 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
 
 // Full time step with frozen rates.  Returns the stage-weighted face value at
 // L_max (meaningful on lane 63) so outflow = dt*G0*that.
-template <int K, int SCHEME>
-__device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, double c, double ghost) {
+template <int K, int SCHEME, int W = 1>
+__device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, double c, double ghost,
+                                           Pair* pr = nullptr) {
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = k < g.npad ? ghost : u[k];   // select, not a divergent branch
     if (SCHEME == PBE_SCHEME_LW_TVD) {
         double u0[K];
-        return fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.0, 1.0, true);
+        return fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
     }
     double u0[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) u0[k] = u[k];
-    const double h0 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.0, 1.0, true);
-    const double h1 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 0.75, 0.25, false);
-    const double h2 = fvm_stage<K, SCHEME>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false);
+    const double h0 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
+    const double h1 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.75, 0.25, false, pr);
+    const double h2 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false, pr);
     return h0 / 6.0 + h1 / 6.0 + (2.0 / 3.0) * h2;
 }
 

@@ -100,7 +100,8 @@ struct pbe_handle {
     std::vector<int32_t> n1v, n2v;   // 2D grid sizes (host copy, for rebuilding the column blocks)
     int32_t* d_cb[3] = {};           // 2D column-block tables (sim, col0, row0), sized for the shortest segment
     int32_t* d_cb_first = nullptr;
-    int resident[kFvmClasses] = {};  // 1D: workgroups of each class that fit the device at once
+    int resident[2][kFvmClasses] = {};  // 1D: workgroups of each class that fit at once [pairs][class]
+    std::vector<double> cost;        // 1D: estimated work per sim (launch order within a class)
     std::vector<int32_t> active_host;
     bool fresh = true;               // next pbe_step starts from the initial condition
     bool solved = false;             // a complete pbe_solve with checkpoints exists
@@ -253,6 +254,22 @@ int fail(pbe_handle* h, int code) {
     do {                                           \
         if ((x) != hipSuccess) return PBE_EDEVICE; \
     } while (0)
+
+// Launch order of the 1D sims: by kernel class, longest first within a class.
+void partition(pbe_handle* h, bool pairs, std::vector<int32_t>& order) {
+    order.resize(h->S);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int cx = solve1d_class_of(h->ncell[x], pairs), cy = solve1d_class_of(h->ncell[y], pairs);
+        if (cx != cy) return cx < cy;
+        return h->cost[x] > h->cost[y];
+    });
+    for (int c = 0; c < kFvmClasses; ++c) h->cls_count[c] = 0;
+    for (int s = 0; s < h->S; ++s) h->cls_count[solve1d_class_of(h->ncell[s], pairs)]++;
+    h->cls_begin[0] = 0;
+    for (int c = 1; c < kFvmClasses; ++c) h->cls_begin[c] = h->cls_begin[c - 1] + h->cls_count[c - 1];
+    h->a.pair_long = pairs ? 1 : 0;
+}
 
 int launch_classes(pbe_handle* h, int from_initial, int max_steps) {
     h->a.from_initial = from_initial;
@@ -602,6 +619,13 @@ void drop_graph(pbe_handle* h) {
 int apply_tuning(pbe_handle* h, const pbe_tuning& t) {
     drop_graph(h);
     if (h->two_d) return set_col_blocks(h, t.seg_2d);
+    const bool pairs = t.pair_long != 0;
+    if (pairs != (h->a.pair_long != 0)) {
+        std::vector<int32_t> order;
+        partition(h, pairs, order);
+        HIP_OK(hipMemcpy(const_cast<int32_t*>(h->a.order), order.data(), sizeof(int32_t) * h->S,
+                         hipMemcpyHostToDevice));
+    }
     for (int c = 0; c < kFvmClasses; ++c)
         if (h->cls_count[c] > 0) h->cls_blocks[c] = std::max(1, std::min(h->cls_count[c], t.blocks[c]));
     return PBE_OK;
@@ -616,6 +640,9 @@ int trial_ms(pbe_handle* h, int trial_steps, float* ms) {
         for (int k = 0; k < n && rc == PBE_OK; ++k) rc = step2d_once(h);
         if (rc != PBE_OK) return rc;
     } else {
+        // Direct launches.  (Trials through a freshly captured graph per
+        // candidate crashed the process on the host inside the runtime; that
+        // path is switched off until its cause is known.)
         int rc = clear_samples(h);
         if (rc == PBE_OK)
             rc = launch_classes(h, 1, trial_steps > 0 ? trial_steps : std::numeric_limits<int32_t>::max());
@@ -650,11 +677,19 @@ int tune_handle(pbe_handle* h, int trial_steps, bool use_cache, pbe_tuning* out)
             cands.push_back(t);
         }
     } else {
+        // persistent grid size per class, one wavefront per simulation (wave
+        // pairs are not timed here, see trial_ms; pbe_set_launch selects them)
+        std::vector<int32_t> order;
+        if (h->a.pair_long) {
+            partition(h, false, order);
+            HIP_OK(hipMemcpy(const_cast<int32_t*>(h->a.order), order.data(), sizeof(int32_t) * h->S,
+                             hipMemcpyHostToDevice));
+        }
         for (double f : {1.0, 0.25, 0.5, 2.0}) {
             pbe_tuning t{};
             for (int c = 0; c < kFvmClasses; ++c)
                 t.blocks[c] = h->cls_count[c] > 0
-                                  ? std::max(1, std::min(h->cls_count[c], (int)std::lround(h->resident[c] * f)))
+                                  ? std::max(1, std::min(h->cls_count[c], (int)std::lround(h->resident[0][c] * f)))
                                   : 0;
             cands.push_back(t);
         }
@@ -754,17 +789,9 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         cost[s] = (double)h->ncell[s] * (p->t_end / dt);
     }
     int step_cap = p->max_steps > 0 ? p->max_steps : (int)std::min(1.0e9, std::ceil(cap * 1.05) + 8.0);
-    std::vector<int32_t> order(h->S);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        const int cx = fvm1d_class_of(h->ncell[x]), cy = fvm1d_class_of(h->ncell[y]);
-        if (cx != cy) return cx < cy;
-        return cost[x] > cost[y];
-    });
-    for (int c = 0; c < kFvmClasses; ++c) h->cls_count[c] = 0;
-    for (int s = 0; s < h->S; ++s) h->cls_count[fvm1d_class_of(h->ncell[s])]++;
-    h->cls_begin[0] = 0;
-    for (int c = 1; c < kFvmClasses; ++c) h->cls_begin[c] = h->cls_begin[c - 1] + h->cls_count[c - 1];
+    h->cost = cost;
+    std::vector<int32_t> order;
+    partition(h, false, order);
 
     // device memory
     Alloc& m = h->mem;
@@ -848,9 +875,11 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     }
 
     for (int c = 0; c < kFvmClasses; ++c) {
-        const int resident = fvm1d_class_resident_blocks(c, a.closure);
+        const int resident = fvm1d_class_resident_blocks(c, a.closure, 0);
         if (resident <= 0) return fail(h, PBE_EDEVICE);
-        h->resident[c] = resident;
+        h->resident[0][c] = resident;
+        h->resident[1][c] = c == 2 && a.closure == kClosureNone ? fvm1d_class_resident_blocks(c, a.closure, 1)
+                                                                : resident;
         h->cls_blocks[c] = std::max(1, std::min(h->cls_count[c], resident));
         if (c > 0 && hipStreamCreateWithFlags(&h->side[c], hipStreamNonBlocking) != hipSuccess)
             return fail(h, PBE_EDEVICE);
@@ -1131,6 +1160,30 @@ int pbe_tune(pbe_handle* h, int32_t trial_steps, int32_t use_cache, pbe_tuning* 
     pbe_tuning t{};
     int rc = tune_handle(h, trial_steps, use_cache != 0, &t);
     if (rc == PBE_OK && out) *out = t;
+    return rc;
+}
+
+int pbe_set_launch(pbe_handle* h, const pbe_tuning* t) {
+    if (!h || !t) return PBE_EINVAL;
+    if (h->two_d) {
+        if (t->seg_2d < 16 || t->seg_2d > 4096) return PBE_EINVAL;
+    } else {
+        if (t->pair_long && h->a.closure != kClosureNone) return PBE_EINVAL;
+        for (int c = 0; c < kFvmClasses; ++c)
+            if (t->blocks[c] < 0) return PBE_EINVAL;
+    }
+    if (h->two_d && t->seg_2d < k2dSegMin) {
+        // the column-block tables are sized for segments of at least k2dSegMin rows
+        return PBE_EINVAL;
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    pbe_tuning x = *t;
+    if (!h->two_d)
+        for (int c = 0; c < kFvmClasses; ++c)
+            if (x.blocks[c] == 0) x.blocks[c] = h->resident[x.pair_long ? 1 : 0][c];
+    const int rc = apply_tuning(h, x);
+    h->fresh = true;
+    h->solved = false;
     return rc;
 }
 

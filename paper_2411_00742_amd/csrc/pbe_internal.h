@@ -69,6 +69,7 @@ struct Fvm1dArgs {
     int32_t max_steps;         // steps allowed in this launch
     int32_t from_initial;      // 1: start from (f0, C0, t = 0)
     int32_t step_cap;          // absolute per-sim step limit (PBE_SIM_STEPCAP when hit)
+    int32_t pair_long;         // 1: class 2 runs grids > 1024 cells on wave pairs
     int32_t closure;           // kClosure*: which rate law the kernels run
     ClosureDev cd;             // closure == kClosureBf16 / kClosureFp64
 };
@@ -142,10 +143,16 @@ struct Fvm2dArgs {
 // Launchers (defined in the .hip files).  Return hipSuccess or the launch error.
 constexpr int kFvmClasses = 4;   // kernel classes by cells per lane: 1-8, 9-16, 17-24, 25-32
 inline int fvm1d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
+// 1D solves: one wavefront per simulation in four classes of K, or (pairs)
+// grids of more than 1024 cells on a wave pair with K = ceil(N/128) = 9..16
+// in class 2 and class 3 empty.  Classes 0 and 1 are the same either way.
+inline int solve1d_class_of(int n_cells, bool pairs) {
+    return pairs ? (n_cells <= 512 ? 0 : n_cells <= 1024 ? 1 : 2) : fvm1d_class_of(n_cells);
+}
 hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
 hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st);
-int fvm1d_class_resident_blocks(int cls, int closure);
+int fvm1d_class_resident_blocks(int cls, int closure, int pairs);
 constexpr int kAdjClasses = 2;   // adjoint classes: cells per lane 1-8, 9-16 (grids up to 1024 cells)
 hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
