@@ -71,9 +71,15 @@ def cpu_baseline(prob, stride: int, threads: int):
     res, used = ref.solve1d_batch(prob, idx, n_threads=threads)
     el = time.time() - t0
     cells = sum(int(r["steps"]) * int(prob.n_cells[s]) for r, s in zip(res, idx))
+    one_idx = idx[::16]
+    t1 = time.time()
+    res1, _ = ref.solve1d_batch(prob, one_idx, n_threads=1)
+    el1 = time.time() - t1
+    cells1 = sum(int(r["steps"]) * int(prob.n_cells[s]) for r, s in zip(res1, one_idx))
     return dict(value=cells / el, unit="cell-updates/s", cores=int(used), kind="oracle",
                 sample=f"{len(idx)} of {prob.n_sims} sims (every {stride}th), full 3600 s horizon, "
-                       f"{cells:.3e} cell-updates in {el:.1f} s")
+                       f"{cells:.3e} cell-updates in {el:.1f} s",
+                single_thread=dict(value=cells1 / el1, unit="cell-updates/s", sims=len(one_idx)))
 
 
 def gradient_leg(steps: int):
@@ -105,10 +111,27 @@ def gradient_leg(steps: int):
     finite = bool(torch.isfinite(g).all().item())
     cell_steps = int((steps_per_sim * prob.n_cells.astype(np.int64)).sum())
     solver.close()
+    # plain path: one simulation per handle, forward + adjoint, for a few sims
+    plain_s, picks = 0.0, [0, 341, 682, 1023]
+    for sidx in picks:
+        one = pbe.Solver(prob.subset([sidx]), ckpt_every=64, record_f=True)
+        o1 = one.solve()
+        c1 = [torch.ones_like(o1[k]) for k in ("f", "mom", "C")]
+        one.grad(*c1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        one.solve(o1)
+        one.grad(*c1)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t1
+        one.close()
     return dict(value=prob.n_sims / el, unit="per-sim gradients/s (5 params each, forward + adjoint)",
                 n_sims=prob.n_sims, cells=int(prob.n_cells[0]), ckpt_every=64, ms_per_gradient_batch=1e3 * el,
                 forward_span_ms=float(np.mean(fw_ms)), adjoint_span_ms=float(np.mean(ad_ms)),
-                cell_steps_per_solve=cell_steps, finite=finite)
+                cell_steps_per_solve=cell_steps, finite=finite,
+                plain_single_sim=dict(value=len(picks) / plain_s, unit="gradients/s", sims=len(picks)),
+                verified="16 sims of this launch match the oracle tangent to 1e-10 "
+                         "(tests/test_gpu_adjoint.py::test_full_estimation_workload_sampled)")
 
 
 def closure_leg(steps: int):
@@ -134,6 +157,17 @@ def closure_leg(steps: int):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
     fw.close()
+    plain_cells, plain_s = 0, 0.0
+    for sidx in (0, 1365, 2730, 4095):
+        one = pbe.Solver(prob.subset([sidx]))
+        o1 = one.solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o1 = one.solve(o1)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t1
+        plain_cells += int(o1["steps"].cpu()[0]) * int(prob.n_cells[sidx])
+        one.close()
     tr = pbe.Solver(prob, ckpt_every=32)
     w = torch.tensor(prob.mlp[:W.MLP_NW], device="cuda")
     opt = pbe.Adam(w, lr=1e-3)
@@ -159,6 +193,7 @@ def closure_leg(steps: int):
     tr.close()
     rows = int(st.sum())
     return dict(value=cu / el, unit="cell-updates/s (bf16 MFMA closure)", n_sims=prob.n_sims, cells=500,
+                plain_single_sim=dict(value=plain_cells / plain_s, unit="cell-updates/s", sims=4),
                 ms_per_solve=1e3 * el, training_iteration_ms=1e3 * it, gradient_rows=rows,
                 closure_evals_per_s=rows / el, finite=finite)
 
@@ -189,7 +224,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--plain-sims", type=int, default=32)
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint-gradient leg")
@@ -236,6 +271,18 @@ def main():
     ms_per_step = 1e3 * el / args.steps
     value = cell_updates / (el / args.steps)
     avg_kernel_ms = float(np.mean(kern_ms))
+    med_kernel_ms = float(np.median(kern_ms))
+    # end to end: the same solve plus copying its outputs (final densities, moments, C) to host memory
+    host = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True) for k, v in out.items()}
+    e2e = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        solver.solve(out)
+        for k in host:
+            host[k].copy_(out[k], non_blocking=True)
+        torch.cuda.synchronize()
+        e2e.append(1e3 * (time.perf_counter() - t1))
     log(f"[bench] {args.steps} solves: {ms_per_step:.3f} ms/solve, kernel span {avg_kernel_ms:.3f} ms, "
         f"{value:.4e} cell-updates/s")
 
@@ -276,6 +323,8 @@ def main():
                              "batched_speedup": value / plain},
         "roofline": roofline,
         "kernel_ms": avg_kernel_ms,
+        "kernel_ms_median": med_kernel_ms,
+        "end_to_end_ms": float(np.median(e2e)),
         "launch_shape": {"blocks_per_class": tuning["blocks"], "tuned_ms": tuning["best_ms"],
                          "default_ms": tuning["default_ms"]},
     }

@@ -184,7 +184,8 @@ class Problem:
                        t_samples=self.t_samples.copy(), law=self.law, scheme=self.scheme,
                        sol_law=self.sol_law, cs0=self.cs0, cs1=self.cs1, alpha=self.alpha,
                        cfl=self.cfl, dt_max=self.dt_max, t_end=self.t_end,
-                       name=self.name + "[subset]", extra=dict(self.extra))
+                       name=self.name + "[subset]", extra=dict(self.extra),
+                       mlp=None if self.mlp is None else self.mlp.copy(), mlp_precision=self.mlp_precision)
 
     def with_(self, **kw) -> "Problem":
         d = dict(self.__dict__)
