@@ -162,6 +162,12 @@ constexpr int fvm_waves_per_simd(int klo, int cl) {
 template <int SCHEME, int KLO, int CL>
 __global__ __launch_bounds__(64, fvm_waves_per_simd(KLO, CL)) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cls_count,
                                                                         int32_t* queue) {
+    // Longer grids get higher issue priority where waves of different classes
+    // share a SIMD: the simulations with the most cells per lane set the
+    // makespan, the short ones fill the gaps.
+    if constexpr (KLO >= 25) __builtin_amdgcn_s_setprio(3);
+    else if constexpr (KLO >= 17) __builtin_amdgcn_s_setprio(2);
+    else if constexpr (KLO >= 9) __builtin_amdgcn_s_setprio(1);
     for (;;) {
         // Every lane executes the atomic (only lane 0 adds 1) and the ticket
         // is lane 0's return value.  Popping inside `if (lane == 0)` instead
