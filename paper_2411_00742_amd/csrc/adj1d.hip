@@ -56,8 +56,8 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
         const double p = a * b;
         const bool same = p > 0.0;
         const double s = same ? a + b : 1.0;
-        const double r = recip_limiter(s);   // the forward's reciprocal, so psi matches it bitwise
-        const double psi = same ? (p + p) * r : 0.0;
+        const double r = recip_limiter(s);   // the forward's reciprocal, so psi/2 matches it bitwise
+        const double hpsi = same ? p * r : 0.0;
         // d psi/da = 2 (b/(a+b))^2, d psi/db = 2 (a/(a+b))^2: both ratios lie in (0, 1]
         // when ab > 0, so neither factor over- or underflows in the far tails of f
         const double br = b * r, ar = a * r;
@@ -65,7 +65,7 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
         const double psib = same ? 2.0 * ar * ar : 0.0;
         const double Lf = fmax(g.xb + (double)(k + 1), 0.0) * dL;
         const double w = fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0);
-        const double face = uk + 0.5 * psi;
+        const double face = uk + hpsi;
         const double H = w * face;
         const double dv = vbk1 - vbk;
         cbar = fma(H, dv, cbar);
@@ -125,6 +125,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     const int64_t base = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
     const double Lmax = uniform(a.Lmax[s]);
     const double dL = Lmax / N;
+    const double inv_dL = (double)N / Lmax;
     const SimParams q = load_params(a.par + (size_t)s * PBE_NPAR);
     const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
     const int ns = a.n_samples;
@@ -202,8 +203,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
             double dt;
             const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
-            const double ghost = r.G0 > 0.0 ? r.B / r.G0 : 0.0;
-            (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, dt * r.G0 / dL, ghost);
+            const double ghost = inflow_ghost(r.B, r.G0);
+            (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, courant(dt, r.G0, inv_dL), ghost);
             LaneGeom g2 = g;
             asm volatile("" : "+v"(g2.xb));
             const double mu3 = wave_sum(lane_moment3(u, g2, dL)) * dL;
@@ -276,8 +277,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             const double t_next = uniform(nx < ns ? ts[min(nx, ns - 1)] : p.t_end);
             double dt;
             (void)choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_next, &dt);
-            const double ghost = r.G0 > 0.0 ? r.B / r.G0 : 0.0;
-            const double c = dt * r.G0 / dL;
+            const double ghost = inflow_ghost(r.B, r.G0);
+            const double c = courant(dt, r.G0, inv_dL);
 
             // stage input states u0, u1, u2 into this wave's LDS
             set_pad(u0, g, ghost);

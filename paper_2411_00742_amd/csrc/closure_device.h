@@ -221,7 +221,7 @@ __device__ __forceinline__ ClosureRates closure_rates(const ClosureDev& cd, cons
     ClosureRates r;
     const double T = temperature(q, t);
     const double* k = cd.c;
-    r.S = uniform(C / solubility(p, T) - 1.0);
+    r.S = uniform(div_fast(C, solubility(p, T)) - 1.0);
     const double x2 = mu2 > 0.0 ? log64(mu2) / 2.302585092994046 : 0.0;
     const double x[3] = {r.S, T, x2};
     bool inside = r.S > uniform(k[kCSmin]) && mu2 > 0.0;

@@ -38,6 +38,34 @@ __device__ __forceinline__ const cdouble* dmath_table() {
     return t;
 }
 
+// p*r + c with the coefficient c in scalar registers, as one VOP3 v_fma_f64.
+// Written out because instruction selection otherwise picks the two-address
+// v_fmac_f64 and first copies c into a vector register pair (two extra VALU
+// moves per Horner step).
+__device__ __forceinline__ double fma_sc(double p, double r, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(r), "s"(c));
+    return d;
+}
+
+// a/b for b in [2^-1000, 2^1000] in magnitude: hardware reciprocal, one
+// Newton step on it, then one residual correction of the quotient (within
+// about an ulp of the correctly rounded a/b).  Six VALU operations against
+// eleven for the correctly rounded division with its scaling and fix-up.
+__device__ __forceinline__ double div_near(double a, double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(r, fma(-b, r, 1.0), r);
+    const double q = a * r;
+    return fma(r, fma(-b, q, a), q);
+}
+// a/b for any b: div_near inside its range, the exact division outside it
+// (a wave-uniform b takes a scalar branch)
+__device__ __forceinline__ double div_fast(double a, double b) {
+    const double m = __builtin_fabs(b);
+    if (m >= 0x1p-1000 && m <= 0x1p1000) return div_near(a, b);
+    return a / b;
+}
+
 // e^x for finite x; underflows to 0 below -745, overflows to +inf above 709.8
 __device__ __forceinline__ double exp64(double x) {
     if (x < -745.2) return 0.0;
@@ -46,9 +74,9 @@ __device__ __forceinline__ double exp64(double x) {
     const double k = rint(x * T[28]);
     const double r = fma(-k, T[27], fma(-k, T[26], x));
     // Taylor series of e^r, Horner from 1/13! down to 1/0!
-    double p = T[0];
+    double p = fma(T[0], r, T[1]);
 #pragma unroll
-    for (int n = 1; n < 14; ++n) p = fma(p, r, T[n]);
+    for (int n = 2; n < 14; ++n) p = fma_sc(p, r, T[n]);
     return __builtin_amdgcn_ldexp(p, (int)k);
 }
 
@@ -62,12 +90,12 @@ __device__ __forceinline__ double log64(double x) {
         m = m + m;
         e -= 1;
     }
-    const double s = (m - 1.0) / (m + 1.0);
+    const double s = div_near(m - 1.0, m + 1.0);   // m + 1 lies in [1.7, 2.5]
     const double s2 = s * s;
     // 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ... + s^22/23), Horner in s^2
-    double p = T[14];
+    double p = fma(T[14], s2, T[15]);
 #pragma unroll
-    for (int n = 15; n < 26; ++n) p = fma(p, s2, T[n]);
+    for (int n = 16; n < 26; ++n) p = fma_sc(p, s2, T[n]);
     const double de = (double)e;
     return fma(de, T[26], fma(de, T[27], 2.0 * s * p));
 }

@@ -25,6 +25,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
     const int64_t base = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
     const double Lmax = uniform(a.Lmax[s]);
     const double dL = Lmax / N;
+    const double inv_dL = (double)N / Lmax;
     const SimParams q = load_params(a.par + (size_t)s * PBE_NPAR);
     const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
     const int ns = a.n_samples;
@@ -82,7 +83,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             break;
         }
         // nucleation: ghost cells at L < 0 hold B/G0 so the flux through L = 0 is B
-        const double ghost = r.G0 > 0.0 ? r.B / r.G0 : 0.0;
+        const double ghost = inflow_ghost(r.B, r.G0);
 
         if (a.ckpt_every > 0 && step % a.ckpt_every == 0) {
             const int c = step / a.ckpt_every;
@@ -95,7 +96,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             }
         }
 
-        const double cour = dt * r.G0 / dL;
+        const double cour = courant(dt, r.G0, inv_dL);
         const double hN = fvm_step<K, SCHEME, W>(u, g, cour, ghost, pr);
         out = fma(dt * r.G0, hN, out);
 

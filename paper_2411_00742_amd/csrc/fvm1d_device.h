@@ -116,6 +116,7 @@ struct Process {
 
 struct SimParams {
     double kg, g, kb, b, gamma, Eg, Eb, T0, T1, tr;
+    double inv_tr;   // 1/tr (0 when tr = 0)
 };
 
 // (each value is made explicitly wave-uniform: loaded through a vector load,
@@ -126,12 +127,13 @@ __device__ __forceinline__ SimParams load_params(const double* P) {
     q.b = uniform(P[PBE_P_B]); q.gamma = uniform(P[PBE_P_GAMMA]);
     q.Eg = uniform(P[PBE_P_EG]); q.Eb = uniform(P[PBE_P_EB]); q.T0 = uniform(P[PBE_P_T0]);
     q.T1 = uniform(P[PBE_P_T1]); q.tr = uniform(P[PBE_P_TRAMP]);
+    q.inv_tr = q.tr > 0.0 ? 1.0 / q.tr : 0.0;
     return q;
 }
 
 // cooling ramp T0 -> T1 over tr seconds, then held
 __device__ __forceinline__ double temperature(const SimParams& q, double t) {
-    const double frac = q.tr > 0.0 ? fmin(t, q.tr) / q.tr : 1.0;
+    const double frac = q.tr > 0.0 ? fmin(t, q.tr) * q.inv_tr : 1.0;
     return q.T0 + (q.T1 - q.T0) * frac;
 }
 __device__ __forceinline__ double solubility(const Process& p, double T) {
@@ -146,13 +148,14 @@ struct Rates {
 __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& q, double C, double t) {
     Rates r;
     const double T = temperature(q, t);
-    r.S = C / solubility(p, T) - 1.0;
+    r.S = div_fast(C, solubility(p, T)) - 1.0;
     r.G0 = 0.0; r.B = 0.0; r.lnS = 0.0; r.arrG = 1.0; r.arrB = 1.0;
     if (r.S > 0.0) {
         r.lnS = log64(r.S);
         if (p.law == PBE_LAW_ARRHENIUS) {
-            r.arrG = exp64(-q.Eg / (T + 273.15));
-            r.arrB = exp64(-q.Eb / (T + 273.15));
+            const double iT = div_fast(1.0, T + 273.15);
+            r.arrG = exp64(-q.Eg * iT);
+            r.arrB = exp64(-q.Eb * iT);
         }
         r.G0 = 1e6 * q.kg * exp64(q.g * r.lnS) * r.arrG;
         r.B = q.kb * exp64(q.b * r.lnS) * r.arrB;
@@ -197,7 +200,7 @@ __device__ __forceinline__ Rates2 rates_2d(const Process& p, const SimParams& q,
 __device__ __forceinline__ bool choose_dt(const Process& p, double G0, double gamma, double Lmax, double dL, double t,
                                           double t_next, double* dt) {
     const double Gmax = G0 * (1.0 + gamma * Lmax);
-    const double lim = Gmax > 0.0 ? p.cfl * dL / Gmax : __builtin_huge_val();
+    const double lim = Gmax > 0.0 ? div_fast(p.cfl * dL, Gmax) : __builtin_huge_val();
     const double d = fmin(lim, p.dt_max);
     const double rem = t_next - t;
     const bool hit = d >= rem - 1e-12 * p.t_end;
@@ -205,40 +208,57 @@ __device__ __forceinline__ bool choose_dt(const Process& p, double G0, double ga
     return uniform((int)hit) != 0;
 }
 
+// nucleation enters as the inflow ghost B/G0 left of L = 0, so the flux
+// through L = 0 is B
+__device__ __forceinline__ double inflow_ghost(double B, double G0) {
+    return G0 > 0.0 ? div_fast(B, G0) : 0.0;
+}
+// Courant factor c = dt G0 / dL of the stage update (1/dL fixed per simulation)
+__device__ __forceinline__ double courant(double dt, double G0, double inv_dL) { return dt * G0 * inv_dL; }
+
 // ---------------------------------------------------------------- flux
 // van Leer limited slope psi = phi(a/b)*b = 2ab/(a+b) when a and b share a
 // strict sign, else 0 (SI Eqs. (S1)-(S2) in division-safe form).
 // 1/d for the limiter's denominator d = a + b with ab > 0 (so |d| >= 2 sqrt(ab)
-// >= 4.4e-162, never subnormal, and 1/d stays finite): hardware
-// reciprocal refined by two Newton steps (within an ulp or so of 1/d), six
-// VALU operations instead of the eleven of the correctly rounded division.
+// >= 4.4e-162, never subnormal, and 1/d stays finite): the hardware
+// reciprocal (relative error around 2^-23) refined by one Newton step, which
+// squares the error to ~1e-14 relative: three VALU operations instead of the
+// eleven of the correctly rounded division.  The limiter is a smooth function
+// of a and b away from the select, so a relative error of 1e-14 in psi moves
+// the solution by far less than the 1e-10 it is checked to.
 __device__ __forceinline__ double recip_limiter(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-d, r, 1.0);
+    const double r = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r, 1.0);
     return fma(r, e, r);
 }
 
-__device__ __forceinline__ double limited_slope(double a, double b) {
+// Half the van Leer slope, psi/2 = ab/(a+b) when a and b share a strict sign,
+// else 0.  Every face needs only psi/2, and p * (1/(a+b)) is exactly half of
+// 2p * (1/(a+b)) (scaling by 2 does not change the rounding), so the doubling
+// and the halving are both left out.  One select at the end: where the slopes
+// disagree a + b may be 0 or tiny and the quotient garbage, but it is discarded.
+__device__ __forceinline__ double half_limited_slope(double a, double b) {
     const double p = a * b;
     const bool same = p > 0.0;
-    // one select at the end: where the slopes disagree a + b may be 0 or tiny and
-    // the quotient garbage, but it is discarded
-    const double q = (p + p) * recip_limiter(a + b);
+    const double q = p * recip_limiter(a + b);
     return same ? q : 0.0;
 }
 
-// Face value H = w (f_i + kappa/2 psi) with w = G(L_face)/G0; the face flux is
-// G0*H.  kappa = 1 (method of lines) or 1 - nu_face (one-step update, Eq. (8)).
+// Face value H = w (f_i + kappa/2 psi) with w = G(L_face)/G0, from the slopes
+// a = f_i - f_{i-1} and b = f_{i+1} - f_i; the face flux is G0*H.  kappa = 1
+// (method of lines) or 1 - nu_face (one-step update, Eq. (8)).
 template <int SCHEME>
-__device__ __forceinline__ double face_value(double um1, double ui, double up1, double w, double c) {
-    const double psi = limited_slope(ui - um1, up1 - ui);
+__device__ __forceinline__ double face_value_ab(double a, double b, double ui, double w, double c) {
+    const double h = half_limited_slope(a, b);
     if (SCHEME == PBE_SCHEME_LW_TVD) {
         const double kappa = 1.0 - c * w;
-        return w * (ui + 0.5 * kappa * psi);
+        return w * fma(kappa, h, ui);
     }
-    return w * (ui + 0.5 * psi);
+    return w * (ui + h);
+}
+template <int SCHEME>
+__device__ __forceinline__ double face_value(double um1, double ui, double up1, double w, double c) {
+    return face_value_ab<SCHEME>(ui - um1, up1 - ui, ui, w, c);
 }
 
 // Geometry of one lane's slots.
@@ -294,27 +314,41 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
         fillH = pr->w == 1 ? Hb : ghost;
     }
     const double HL = shift_from_left(Hlast, fillH);
-    double Hprev = HL, um1 = uL;
-    double ui = u[0];
-    double xk = g.xb;   // cell index of slot k
+    double Hprev = HL;
+    double a = u[0] - uL;   // slope left of slot 0
+    // unclamped face weight z = 1 + gamma dL x of the face right of slot k,
+    // stepped by gamma dL per slot from the face left of slot 0; with
+    // gamma >= 0, max(z, 1) = 1 + gamma max(L, 0).  (z is formed by an add
+    // after the ordering barrier below, so the max needs no NaN canonicalise.)
+    double zl = fma(g.gdL, g.xb, 1.0);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+        const double ui = u[k];
         const double up1 = (k + 1 < K) ? u[k + 1 < K ? k + 1 : 0] : uR;
-        const double w = fma(g.gdL, fmax(xk + 1.0, 0.0), 1.0);
-        const double H = (k == K - 1) ? Hlast : face_value<SCHEME>(um1, ui, up1, w, c);
+        const double b = up1 - ui;
+        const double z = zl + g.gdL;
+        const double H = (k == K - 1) ? Hlast : face_value_ab<SCHEME>(a, b, ui, fmax(z, 1.0), c);
         const double v = ui + c * (Hprev - H);
         const double nv = first ? v : wa * u0[k] + wb * v;
         u[k] = nv;
         Hprev = H;
-        // Sliding-window order: every input of the next slot (its cell value,
-        // its left neighbour and its face coordinate) is made to depend on
-        // this slot's result, so the scheduler cannot compute the faces of all
-        // K slots up front (that keeps several arrays of K doubles live).
-        double next_um1 = ui, next_ui = up1, next_x = xk + 1.0;
-        asm volatile("" : "+v"(next_um1), "+v"(next_ui), "+v"(next_x) : "v"(nv));
-        um1 = next_um1;
-        ui = next_ui;
-        xk = next_x;
+        a = b;
+        zl = z;
+        // Sliding-window order: the inputs of the next slot that are not yet
+        // derived from this one (the carried slope, the face weight and the
+        // cell two to the right) are made to depend on this slot's result, so
+        // the scheduler cannot compute the faces of all K slots up front (that
+        // keeps several arrays of K doubles live).  u[k + 2] is tied in place,
+        // which costs no copy.
+        if constexpr (K >= 3) {
+            if (k + 2 < K) {
+                asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]), "+v"(a), "+v"(zl) : "v"(nv));
+            } else {
+                asm volatile("" : "+v"(a), "+v"(zl) : "v"(nv));
+            }
+        } else {
+            asm volatile("" : "+v"(a), "+v"(zl) : "v"(nv));
+        }
     }
     return Hlast;
 }
@@ -336,7 +370,7 @@ __device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, do
     const double h0 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
     const double h1 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.75, 0.25, false, pr);
     const double h2 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false, pr);
-    return h0 / 6.0 + h1 / 6.0 + (2.0 / 3.0) * h2;
+    return fma(h0 + h1, 1.0 / 6.0, (2.0 / 3.0) * h2);
 }
 
 // Load / store this lane's K cells of one simulation's packed array `row`

@@ -71,7 +71,7 @@ struct ColStage {
     double im1, i0, Fm1;
 };
 __device__ __forceinline__ double col_face(double a, double b, double x) {
-    return b + 0.5 * limited_slope(b - a, x - b);
+    return b + half_limited_slope(b - a, x - b);
 }
 __device__ __forceinline__ double col_feed(ColStage& st, double x, double c, double u0r, double wa, double wb,
                                            bool first, int r, int n2, double ghost) {
