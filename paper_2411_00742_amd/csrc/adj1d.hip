@@ -126,6 +126,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     const double Lmax = uniform(a.Lmax[s]);
     const double dL = Lmax / N;
     const double inv_dL = (double)N / Lmax;
+    const double dL3 = dL * dL * dL, dL4 = dL3 * dL;   // moment scales in cell units
     const SimParams q = load_params(a.par + (size_t)s * PBE_NPAR);
     const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
     const int ns = a.n_samples;
@@ -171,9 +172,10 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         double C = uniform(a.ck_C[(int64_t)s * a.n_ckpt + seg]);
         double t = uniform(a.ck_t[(int64_t)s * a.n_ckpt + seg]);
         int next = samples_reached(ts, ns, t);
+        double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
         LaneGeom gm = g;
         asm volatile("" : "+v"(gm.xb));
-        double mu3_old = wave_sum(lane_moment3(u, gm, dL)) * dL;
+        double mu3_old = wave_sum(lane_moment3(u, gm)) * dL4;
         for (int m = m0; m < m1; ++m) {
             store_cells(u, tape + (int64_t)(m - m0) * N, i0, g.npad);
             if (lane == 0) {
@@ -187,7 +189,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 // closure with the forward tangents d/dz0, d/dz2; taped for the reverse walk
                 LaneGeom g2 = g;
                 asm volatile("" : "+v"(g2.xb));
-                const double mu2 = wave_sum(lane_moment2(u, g2, dL)) * dL;
+                const double mu2 = wave_sum(lane_moment2(u, g2)) * dL3;
                 const ClosureRates cr = closure_rates<true, CL>(a.cd, p, q, C, t, mu2);
                 r.G0 = cr.G0;
                 r.B = cr.B;
@@ -200,18 +202,20 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     tr[10] = mu2;
                 }
             }
-            const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
             double dt;
             const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
             const double ghost = inflow_ghost(r.B, r.G0);
             (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, courant(dt, r.G0, inv_dL), ghost);
             LaneGeom g2 = g;
             asm volatile("" : "+v"(g2.xb));
-            const double mu3 = wave_sum(lane_moment3(u, g2, dL)) * dL;
+            const double mu3 = wave_sum(lane_moment3(u, g2)) * dL4;
             C = uniform(C - p.alpha * (mu3 - mu3_old));
             mu3_old = mu3;
             t = uniform(hit ? t_next : t + dt);
-            if (hit) next = samples_reached(ts, ns, t);
+            if (hit) {
+                next = samples_reached(ts, ns, t);
+                t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
+            }
         }
         // (each lane reads back only the tape addresses it wrote itself)
 
@@ -237,7 +241,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     for (int k = 0; k < K; ++k) gcell[k] = 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const double x = g3.xb + (double)k + 0.5;
+                    const double x = g3.xb + ((double)k + 0.5);
                     const double L = fmax(x, 0.0) * dL;
                     const double add = ((gm4[3] * L + gm4[2]) * L + gm4[1]) * L * dL + gm4[0] * dL + gcell[k];
                     lam[k] += x > 0.0 ? add : 0.0;
@@ -304,7 +308,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 asm volatile("" : "+v"(g4.xb));
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const double L = fmax(g4.xb + (double)k + 0.5, 0.0) * dL;
+                    const double L = fmax(g4.xb + ((double)k + 0.5), 0.0) * dL;
                     const double lp = lam[k] - p.alpha * lamC * (L * L * L * dL);
                     ub[k] = (2.0 / 3.0) * lp;   // vbar of stage 3
                     l0[k] = (1.0 / 3.0) * lp;
@@ -326,7 +330,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 for (int k = 0; k < K; ++k) {
                     const double l = l0[k] + ub[k];
                     const bool padk = k < g5.npad;   // pad slots were set to the ghost at the step start
-                    const double L = fmax(g5.xb + (double)k + 0.5, 0.0) * dL;
+                    const double L = fmax(g5.xb + ((double)k + 0.5), 0.0) * dL;
                     gbar += padk ? l : 0.0;
                     lam[k] = padk ? 0.0 : fma(p.alpha * lamC, L * L * L * dL, l);
                 }
@@ -353,7 +357,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 asm volatile("" : "+v"(g6.xb));
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const double x = g6.xb + (double)k + 0.5;
+                    const double x = g6.xb + ((double)k + 0.5);
                     const double L = fmax(x, 0.0) * dL;
                     lam[k] += x > 0.0 ? mbar * (L * L * dL) : 0.0;
                 }

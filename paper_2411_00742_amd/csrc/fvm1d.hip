@@ -26,6 +26,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
     const double Lmax = uniform(a.Lmax[s]);
     const double dL = Lmax / N;
     const double inv_dL = (double)N / Lmax;
+    const double dL3 = dL * dL * dL, dL4 = dL3 * dL;   // moment scales in cell units
     const SimParams q = load_params(a.par + (size_t)s * PBE_NPAR);
     const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
     const int ns = a.n_samples;
@@ -46,7 +47,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
     if (a.from_initial) {
         C = uniform(a.C0[s]);
         t = 0.0;
-        mu3_old = group_sum<W>(wave_sum(lane_moment3(u, g, dL)), pr) * dL;
+        mu3_old = group_sum<W>(wave_sum(lane_moment3(u, g)), pr) * dL4;
         out = 0.0;
         step = 0; next = 0; status = 0;
     } else {
@@ -55,6 +56,11 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
     }
     C = uniform(C); t = uniform(t); mu3_old = uniform(mu3_old);
     step = uniform(step); next = uniform(next); status = uniform(status);
+    // next sample time (reloaded only when a sample is taken) and the next
+    // checkpoint (index and step), so no step pays a load or a division for them
+    double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
+    int ck_c = a.ckpt_every > 0 ? (step + a.ckpt_every - 1) / a.ckpt_every : 0;
+    int ck_at = a.ckpt_every > 0 ? ck_c * a.ckpt_every : -1;
 
     for (int it = 0; it < a.max_steps; ++it) {
         if (!(t < p.t_end) || (status & PBE_SIM_NONFINITE)) break;
@@ -68,14 +74,13 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             // learned closure: inputs S, T and mu_2 of the current state
             LaneGeom g2 = g;
             asm volatile("" : "+v"(g2.xb));
-            const double mu2 = wave_sum(lane_moment2(u, g2, dL)) * dL;
+            const double mu2 = wave_sum(lane_moment2(u, g2)) * dL3;
             const ClosureRates cr = closure_rates<false, CL>(a.cd, p, q, C, t, mu2);
             r.G0 = cr.G0;
             r.B = cr.B;
             r.S = cr.S;
             if (cr.fallback) status |= PBE_SIM_FALLBACK;
         }
-        const double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
         double dt;
         const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
         if (!(dt > 0.0) || !isfinite(dt)) {   // rates overflowed: stop this sim
@@ -85,8 +90,9 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         // nucleation: ghost cells at L < 0 hold B/G0 so the flux through L = 0 is B
         const double ghost = inflow_ghost(r.B, r.G0);
 
-        if (a.ckpt_every > 0 && step % a.ckpt_every == 0) {
-            const int c = step / a.ckpt_every;
+        if (step == ck_at) {
+            const int c = ck_c++;
+            ck_at += a.ckpt_every;
             if (c < a.n_ckpt) {
                 store_cells(u, a.ck_f + base * a.n_ckpt + (int64_t)c * N, i0, g.npad);
                 if (lane == 0) {
@@ -103,7 +109,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         // discrete solute balance, Eq. (9): C^{n+1} = C^n - alpha (mu3^{n+1} - mu3^n)
         LaneGeom gm = g;
         asm volatile("" : "+v"(gm.xb));
-        const double mu3 = group_sum<W>(wave_sum(lane_moment3(u, gm, dL)), pr) * dL;
+        const double mu3 = group_sum<W>(wave_sum(lane_moment3(u, gm)), pr) * dL4;
         C = uniform(C - p.alpha * (mu3 - mu3_old));
         mu3_old = mu3;
         t = uniform(hit ? t_next : t + dt);
@@ -130,6 +136,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
                 if (a.record_f) store_cells(u, a.f_s + base * ns + (int64_t)next * N, i0, g.npad);
                 ++next;
             }
+            t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
         }
     }
 

@@ -37,11 +37,12 @@ __device__ __forceinline__ double shift_from_right(double v, double fill) {
     const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x130, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double v) {
-    // rows outside ROW_MASK (and invalid source lanes) read 0
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+// every lane reads v from its DPP source lane (0 where it has none); no
+// previous-value operand, so no fill copy is needed
+template <int CTRL>
+__device__ __forceinline__ double dpp_src(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_value(double v, int lane) {
@@ -61,14 +62,18 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // Sum over the 64 lanes with DPP (pairs, quads, half rows, rows, then the
 // row broadcasts); the total lands in lane 63 and is read back as a
-// wave-uniform scalar, so everything computed from it stays scalar.
+// wave-uniform scalar, so everything computed from it stays scalar.  After
+// the first four steps every lane holds its row's sum R_r; row_bcast:15 adds
+// R_{r-1} to row r and row_bcast:31 adds row 1's value (R_0 + R_1) to rows 2
+// and 3, so row 3 ends with R_0 + R_1 + R_2 + R_3.  Other lanes end with
+// partial sums nobody reads, which lets every DPP move run on all rows.
 __device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_move<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-    v += dpp_move<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-    v += dpp_move<0x141, 0xF>(v);   // row_half_mirror
-    v += dpp_move<0x140, 0xF>(v);   // row_mirror
-    v += dpp_move<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-    v += dpp_move<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    v += dpp_src<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_src<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_src<0x141>(v);   // row_half_mirror
+    v += dpp_src<0x140>(v);   // row_mirror
+    v += dpp_src<0x142>(v);   // row_bcast:15
+    v += dpp_src<0x143>(v);   // row_bcast:31
     return lane_value(v, 63);
 }
 
@@ -339,16 +344,9 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
         // cell two to the right) are made to depend on this slot's result, so
         // the scheduler cannot compute the faces of all K slots up front (that
         // keeps several arrays of K doubles live).  u[k + 2] is tied in place,
-        // which costs no copy.
-        if constexpr (K >= 3) {
-            if (k + 2 < K) {
-                asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]), "+v"(a), "+v"(zl) : "v"(nv));
-            } else {
-                asm volatile("" : "+v"(a), "+v"(zl) : "v"(nv));
-            }
-        } else {
-            asm volatile("" : "+v"(a), "+v"(zl) : "v"(nv));
-        }
+        // which costs no copy.  The last slot takes Hlast, computed up front,
+        // and needs neither the slope nor the weight.
+        if (k + 2 < K) asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]), "+v"(a), "+v"(zl) : "v"(nv));
     }
     return Hlast;
 }
@@ -401,25 +399,27 @@ __device__ __forceinline__ void store_cells(const double (&u)[K], double* row, i
         if (k >= npad) lp[k] = u[k];
 }
 
-// this lane's part of sum_i L_i^3 f_i (cell centres; pad slots weigh 0)
+// this lane's part of sum_i x_i^3 f_i, x_i = L_i/dL the cell centre in cell
+// widths (pad slots weigh 0); mu_3 = dL^4 times the wave's sum
 template <int K>
-__device__ __forceinline__ double lane_moment3(const double (&u)[K], const LaneGeom& g, double dL) {
+__device__ __forceinline__ double lane_moment3(const double (&u)[K], const LaneGeom& g) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double L = fmax(g.xb + (double)k + 0.5, 0.0) * dL;
-        s = fma(L * L * L, u[k], s);
+        const double x = fmax(g.xb + ((double)k + 0.5), 0.0);
+        s = fma(x * x * x, u[k], s);
     }
     return s;
 }
 
+// the same for x_i^2 f_i; mu_2 = dL^3 times the wave's sum
 template <int K>
-__device__ __forceinline__ double lane_moment2(const double (&u)[K], const LaneGeom& g, double dL) {
+__device__ __forceinline__ double lane_moment2(const double (&u)[K], const LaneGeom& g) {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double L = fmax(g.xb + (double)k + 0.5, 0.0) * dL;
-        s = fma(L * L, u[k], s);
+        const double x = fmax(g.xb + ((double)k + 0.5), 0.0);
+        s = fma(x * x, u[k], s);
     }
     return s;
 }
@@ -429,7 +429,7 @@ __device__ __forceinline__ void lane_moments(const double (&u)[K], const LaneGeo
     m[0] = m[1] = m[2] = m[3] = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double x = g.xb + (double)k + 0.5;
+        const double x = g.xb + ((double)k + 0.5);
         const double L = fmax(x, 0.0) * dL;
         const double f = x > 0.0 ? u[k] : 0.0;
         m[0] += f;
