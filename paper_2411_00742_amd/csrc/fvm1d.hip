@@ -167,7 +167,18 @@ constexpr int fvm_waves_per_simd(int klo, int cl) {
     return cl != 0 ? (klo == 1 ? 3 : 2) : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
 }
 
-template <int SCHEME, int KLO, int CL>
+// run simulation s with its K (uniform) in [KA, KHI]: a chain of scalar branches
+template <int KA, int KHI, int SCHEME, int CL>
+__device__ __forceinline__ void run_k(const Fvm1dArgs& a, int s, int K) {
+    if constexpr (KA <= KHI) {
+        if (K == KA)
+            run_sim<KA, SCHEME, CL, 1>(a, s, nullptr);
+        else
+            run_k<KA + 1, KHI, SCHEME, CL>(a, s, K);
+    }
+}
+
+template <int SCHEME, int KLO, int KHI, int CL>
 __global__ __launch_bounds__(64, fvm_waves_per_simd(KLO, CL)) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cls_count,
                                                                         int32_t* queue) {
     // Longer grids get higher issue priority where waves of different classes
@@ -187,17 +198,7 @@ __global__ __launch_bounds__(64, fvm_waves_per_simd(KLO, CL)) void k_fvm1d(Fvm1d
         if (idx >= cls_count) break;
         const int s = uniform(a.order[cls_begin + idx]);
         const int K = uniform((a.ncell[s] + 63) >> 6);
-        switch (K - KLO) {
-            case 0: run_sim<KLO + 0, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 1: run_sim<KLO + 1, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 2: run_sim<KLO + 2, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 3: run_sim<KLO + 3, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 4: run_sim<KLO + 4, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 5: run_sim<KLO + 5, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 6: run_sim<KLO + 6, SCHEME, CL, 1>(a, s, nullptr); break;
-            case 7: run_sim<KLO + 7, SCHEME, CL, 1>(a, s, nullptr); break;
-            default: break;
-        }
+        run_k<KLO, KHI, SCHEME, CL>(a, s, K);
     }
 }
 
@@ -250,15 +251,15 @@ static hipError_t launch_class(int cls, const Fvm1dArgs& a, int n_blocks, int be
                                hipStream_t st) {
     constexpr int N = kClosureNone;
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_fvm1d<SCHEME, 1, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        case 1: hipLaunchKernelGGL((k_fvm1d<SCHEME, 9, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 0: hipLaunchKernelGGL((k_fvm1d<SCHEME, 1, 8, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 1: hipLaunchKernelGGL((k_fvm1d<SCHEME, 9, 16, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
         case 2:
             if (a.pair_long)
                 hipLaunchKernelGGL((k_fvm1d_pair<SCHEME>), dim3(n_blocks), dim3(128), 0, st, a, begin, count, q);
             else
-                hipLaunchKernelGGL((k_fvm1d<SCHEME, 17, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
+                hipLaunchKernelGGL((k_fvm1d<SCHEME, 17, 24, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
             break;
-        default: hipLaunchKernelGGL((k_fvm1d<SCHEME, 25, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        default: hipLaunchKernelGGL((k_fvm1d<SCHEME, 25, 32, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
     }
     return hipGetLastError();
 }
@@ -269,8 +270,8 @@ static hipError_t launch_closure_class(int cls, const Fvm1dArgs& a, int n_blocks
                                        hipStream_t st) {
     constexpr int R = PBE_SCHEME_SSPRK3;
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_fvm1d<R, 1, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        case 1: hipLaunchKernelGGL((k_fvm1d<R, 9, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 0: hipLaunchKernelGGL((k_fvm1d<R, 1, 8, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 1: hipLaunchKernelGGL((k_fvm1d<R, 9, 16, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -293,12 +294,12 @@ template <int CL>
 static hipError_t occupancy(int cls, int pairs, int* per_cu) {
     constexpr int R = PBE_SCHEME_SSPRK3;
     switch (cls) {
-        case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 1, CL>, 64, 0);
-        case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 9, CL>, 64, 0);
+        case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 1, 8, CL>, 64, 0);
+        case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 9, 16, CL>, 64, 0);
         case 2:
             if (pairs) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d_pair<R>, 128, 0);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 17, kClosureNone>, 64, 0);
-        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 25, kClosureNone>, 64, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 17, 24, kClosureNone>, 64, 0);
+        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 25, 32, kClosureNone>, 64, 0);
     }
 }
 

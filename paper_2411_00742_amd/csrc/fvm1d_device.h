@@ -278,10 +278,14 @@ __device__ __forceinline__ double face_weight(const LaneGeom& g, int k) {
     return fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0);
 }
 
+// slots in flight in the stage loop (see the ordering barrier in fvm_stage)
+template <int K>
+constexpr int kStageLag = 1;
+
 // One Runge-Kutta stage on the wavefront's cells:
 //   v = u + c (H_{i-1/2} - H_{i+1/2}),   u <- first ? v : wa*u0 + wb*v
 // with c = dt*G0/dL.  Returns this lane's last face value (lane 63: L_max).
-template <int K, int SCHEME, int W = 1>
+template <int K, int SCHEME, int W = 1, int LAG = kStageLag<K>>
 __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K], LaneGeom g, double c,
                                             double ghost, double wa, double wb, bool first, Pair* pr = nullptr) {
     static_assert(W == 1 || K >= 2, "wave pairs hold at least two cells per lane");
@@ -326,6 +330,7 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
     // gamma >= 0, max(z, 1) = 1 + gamma max(L, 0).  (z is formed by an add
     // after the ordering barrier below, so the max needs no NaN canonicalise.)
     double zl = fma(g.gdL, g.xb, 1.0);
+    double nv_prev = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double ui = u[k];
@@ -346,28 +351,37 @@ __device__ __forceinline__ double fvm_stage(double (&u)[K], const double (&u0)[K
         // keeps several arrays of K doubles live).  u[k + 2] is tied in place,
         // which costs no copy.  The last slot takes Hlast, computed up front,
         // and needs neither the slope nor the weight.
-        if (k + 2 < K) asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]), "+v"(a), "+v"(zl) : "v"(nv));
+        // With LAG = 2 the next slot waits for the slot before this one
+        // instead, so two slots are in flight: more registers, more overlap
+        // of the dependent FP64 chains for the long grids that run alone on
+        // a SIMD.
+        if constexpr (LAG == 1) {
+            if (k + 2 < K) asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]), "+v"(a), "+v"(zl) : "v"(nv));
+        } else {
+            if (k + 2 < K) asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]), "+v"(a), "+v"(zl) : "v"(nv_prev));
+            nv_prev = nv;
+        }
     }
     return Hlast;
 }
 
 // Full time step with frozen rates.  Returns the stage-weighted face value at
 // L_max (meaningful on lane 63) so outflow = dt*G0*that.
-template <int K, int SCHEME, int W = 1>
+template <int K, int SCHEME, int W = 1, int LAG = kStageLag<K>>
 __device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, double c, double ghost,
                                            Pair* pr = nullptr) {
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = k < g.npad ? ghost : u[k];   // select, not a divergent branch
     if (SCHEME == PBE_SCHEME_LW_TVD) {
         double u0[K];
-        return fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
+        return fvm_stage<K, SCHEME, W, LAG>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
     }
     double u0[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) u0[k] = u[k];
-    const double h0 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
-    const double h1 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 0.75, 0.25, false, pr);
-    const double h2 = fvm_stage<K, SCHEME, W>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false, pr);
+    const double h0 = fvm_stage<K, SCHEME, W, LAG>(u, u0, g, c, ghost, 0.0, 1.0, true, pr);
+    const double h1 = fvm_stage<K, SCHEME, W, LAG>(u, u0, g, c, ghost, 0.75, 0.25, false, pr);
+    const double h2 = fvm_stage<K, SCHEME, W, LAG>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false, pr);
     return fma(h0 + h1, 1.0 / 6.0, (2.0 / 3.0) * h2);
 }
 

@@ -422,7 +422,7 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
         h->row_begin[c] = (int)row_sim.size();
         for (int s = 0; s < S; ++s) {
             const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
-            if (fvm1d_class_of(n1) != c) continue;
+            if (rows2d_class_of(n1) != c) continue;
             for (int j = 0; j < n2; ++j) {
                 row_sim.push_back(s);
                 row_j.push_back(j);

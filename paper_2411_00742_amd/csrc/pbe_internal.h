@@ -141,11 +141,21 @@ struct Fvm2dArgs {
 };
 
 // Launchers (defined in the .hip files).  Return hipSuccess or the launch error.
-constexpr int kFvmClasses = 4;   // kernel classes by cells per lane: 1-8, 9-16, 17-24, 25-32
-inline int fvm1d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
-// 1D solves: one wavefront per simulation in four classes of K, or (pairs)
-// grids of more than 1024 cells on a wave pair with K = ceil(N/128) = 9..16
-// in class 2 and class 3 empty.  Classes 0 and 1 are the same either way.
+// 1D solve kernel classes by cells per lane K = ceil(N/64): class c covers
+// kSolveKlo[c] <= K < kSolveKlo[c + 1].  The last class holds the grids that
+// need the whole register file (one wave per SIMD).
+constexpr int kFvmClasses = 4;
+constexpr int kSolveKlo[kFvmClasses + 1] = {1, 9, 17, 25, 33};
+inline int fvm1d_class_of(int n_cells) {
+    const int K = (n_cells + 63) / 64;
+    return K < kSolveKlo[1] ? 0 : K < kSolveKlo[2] ? 1 : K < kSolveKlo[3] ? 2 : 3;
+}
+// 2D row sweeps: classes of eight cells per lane (1-8, ..., 25-32)
+constexpr int kRowClasses = 4;
+inline int rows2d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
+// 1D solves: one wavefront per simulation in the four classes above, or
+// (pairs) grids of more than 1024 cells on a wave pair with K = ceil(N/128) =
+// 9..16 in class 2 and class 3 empty.  Classes 0 and 1 are the same either way.
 inline int solve1d_class_of(int n_cells, bool pairs) {
     return pairs ? (n_cells <= 512 ? 0 : n_cells <= 1024 ? 1 : 2) : fvm1d_class_of(n_cells);
 }
@@ -157,7 +167,6 @@ constexpr int kAdjClasses = 2;   // adjoint classes: cells per lane 1-8, 9-16 (g
 hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
 int adj1d_class_resident_blocks(int cls, int closure);
-constexpr int kRowClasses = 4;   // row sweep classes by cells per lane (rows up to 2048 cells)
 hipError_t launch_rows2d(int cls, const Fvm2dArgs& a, int parity, int begin, int count, hipStream_t st);
 hipError_t launch_cols2d(const Fvm2dArgs& a, int parity, hipStream_t st);
 hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st);
