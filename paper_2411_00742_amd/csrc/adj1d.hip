@@ -46,36 +46,37 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
     double send_left = 0.0;   // -abar of slot 0: belongs to the left neighbour's last cell
     double carry = 0.0;       // bbar of slot k-1 to add to slot k
     double vbk = vb0;         // original vbar_k
-    double um1 = uL;
     double uk = us[lane];
+    double a = uk - uL;       // slope left of slot 0 (then carried from slot to slot)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double up1 = (k + 1 < K) ? us[(k + 1) * 64 + lane] : uR;
         const double vbk1 = (k + 1 < K) ? ub[k + 1 < K ? k + 1 : 0] : vbR;   // still original here
-        const double a = uk - um1, b = up1 - uk;
+        const double b = up1 - uk;
         const double p = a * b;
         const bool same = p > 0.0;
-        const double s = same ? a + b : 1.0;
-        const double r = recip_limiter(s);   // the forward's reciprocal, so psi/2 matches it bitwise
-        const double hpsi = same ? p * r : 0.0;
-        // d psi/da = 2 (b/(a+b))^2, d psi/db = 2 (a/(a+b))^2: both ratios lie in (0, 1]
-        // when ab > 0, so neither factor over- or underflows in the far tails of f
+        // the forward's reciprocal where the limiter is active (so psi/2 = p r
+        // matches the forward bitwise) and 0 where it is not, which zeroes
+        // psi/2 and both its derivatives with one select
+        const double r = same ? recip_limiter(a + b) : 0.0;
+        const double hpsi = p * r;
+        // d(psi/2)/da = (b/(a+b))^2, d(psi/2)/db = (a/(a+b))^2: both ratios lie in
+        // (0, 1] when ab > 0, so neither factor over- or underflows in the far tails of f
         const double br = b * r, ar = a * r;
-        const double psia = same ? 2.0 * br * br : 0.0;
-        const double psib = same ? 2.0 * ar * ar : 0.0;
-        const double Lf = fmax(g.xb + (double)(k + 1), 0.0) * dL;
-        const double w = fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0);
+        const double xf = fmax(g.xb + (double)(k + 1), 0.0);
+        const double Lf = xf * dL;
+        const double w = fma(g.gdL, xf, 1.0);
         const double face = uk + hpsi;
         const double H = w * face;
         const double dv = vbk1 - vbk;
         cbar = fma(H, dv, cbar);
         const double Hb = c * dv;
         gam = fma(Hb * face, Lf, gam);
-        const double pb = 0.5 * Hb * w;
-        const double ab = pb * psia;
-        const double bb = pb * psib;
+        const double pb = Hb * w;   // adjoint of the face value f_k + psi_k/2 (times -1 for the right cell)
+        const double ab = pb * (br * br);
+        const double bb = pb * (ar * ar);
         // ubar_k = vbar_k (direct term) + face terms + what slot k-1 pushed right
-        const double ubk = vbk + Hb * w + ab - bb + carry;
+        const double ubk = vbk + pb + ab - bb + carry;
         if (k == 0) {
             send_left = -ab;
         } else {
@@ -84,11 +85,10 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
         ub[k] = ubk;
         carry = bb;
         vbk = vbk1;
-        // sliding-window order (see fvm_stage): the next slot starts after this one
-        double next_um1 = uk;
-        asm volatile("" : "+v"(next_um1) : "v"(ubk));
-        um1 = next_um1;
+        a = b;
         uk = up1;
+        // sliding-window order (see fvm_stage): the next slot starts after this one
+        asm volatile("" : "+v"(a) : "v"(ubk));
     }
     // bbar of the last slot goes to the right neighbour's slot 0; -abar of
     // slot 0 to the left neighbour's last slot (lane 0: to the ghost)
@@ -155,6 +155,14 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     double gk[4] = {0.0, 0.0, 0.0, 0.0};
     double gam = 0.0;
     int qs = ns - 1;   // next sample (from the end) whose cotangent is still to be added
+    // step index of sample qs, and the bracket of sample times around the
+    // reverse walk's current time (nx samples lie at or before it; t_lo is the
+    // last of them, t_hi the next): carried across steps and reloaded only
+    // when they change, so no step waits on a memory round trip for them
+    int qstep = qs >= 0 ? uniform(a.samp_step[(int64_t)s * ns + qs]) : -1;
+    int nx = ns;
+    double t_lo = ns > 0 ? uniform(ts[ns - 1]) : -__builtin_huge_val();
+    double t_hi = p.t_end;
 
     double* tape = A.tape + base * Kc;
     double* tapeC = A.tape_C + (int64_t)s * Kc;
@@ -220,9 +228,21 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         // (each lane reads back only the tape addresses it wrote itself)
 
         // ---- reverse walk over the segment
+        // taped scalars of the first reverse step; each step prefetches the next one's
+        double Cn = uniform(tapeC[m1 - 1 - m0]);
+        double tn = uniform(tapeT[m1 - 1 - m0]);
         for (int m = m1; m > m0; --m) {
+            // state at m-1 from the tape: issued first, consumed after the rates
+            double u0[K];
+            load_cells(u0, tape + (int64_t)(m - 1 - m0) * N, i0, g.npad, 0.0);
+            const double Cm = Cn;
+            const double tm = tn;
+            if (m - 1 > m0) {
+                Cn = uniform(tapeC[m - 2 - m0]);
+                tn = uniform(tapeT[m - 2 - m0]);
+            }
             // cotangents of the samples taken at state m
-            while (qs >= 0 && a.samp_step[(int64_t)s * ns + qs] == m) {
+            while (qs >= 0 && qstep == m) {
                 const int64_t o = (int64_t)s * ns + qs;
                 const double gc = A.gC ? A.gC[o] : 0.0;
                 lamC += gc;
@@ -247,14 +267,15 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     lam[k] += x > 0.0 ? add : 0.0;
                 }
                 --qs;
+                qstep = qs >= 0 ? uniform(a.samp_step[(int64_t)s * ns + qs]) : -1;
             }
 
-            // state at m-1 from the tape
-            double u0[K];
-            load_cells(u0, tape + (int64_t)(m - 1 - m0) * N, i0, g.npad, 0.0);
-            const double Cm = uniform(tapeC[m - 1 - m0]);
-            const double tm = uniform(tapeT[m - 1 - m0]);
-            const int nx = samples_reached(ts, ns, tm);
+            // samples reached at tm (the forward's sample index at step m-1)
+            while (nx > 0 && t_lo > tm) {
+                --nx;
+                t_hi = t_lo;
+                t_lo = nx > 0 ? uniform(ts[nx - 1]) : -__builtin_huge_val();
+            }
             Rates r;
             bool fb = true;   // plain power law at this step
             double cz[3] = {0.0, 0.0, 0.0}, cj[4] = {0.0, 0.0, 0.0, 0.0}, cmu2 = 0.0;
@@ -278,9 +299,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     cmu2 = uniform(tr[10]);
                 }
             }
-            const double t_next = uniform(nx < ns ? ts[min(nx, ns - 1)] : p.t_end);
             double dt;
-            (void)choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_next, &dt);
+            (void)choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_hi, &dt);
             const double ghost = inflow_ghost(r.B, r.G0);
             const double c = courant(dt, r.G0, inv_dL);
 
