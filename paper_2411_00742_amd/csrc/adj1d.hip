@@ -48,9 +48,13 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
     double vbk = vb0;         // original vbar_k
     double uk = us[lane];
     double a = uk - uL;       // slope left of slot 0 (then carried from slot to slot)
+    // stage inputs are read from LDS two slots ahead (the memory clobber on the
+    // ordering barrier keeps each read in front of it), so no slot waits on LDS
+    double pre = K >= 2 ? us[(K >= 2 ? 1 : 0) * 64 + lane] : uR;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const double up1 = (k + 1 < K) ? us[(k + 1) * 64 + lane] : uR;
+        const double up1 = (k + 1 < K) ? pre : uR;
+        if (k + 2 < K) pre = us[(k + 2 < K ? k + 2 : 0) * 64 + lane];
         const double vbk1 = (k + 1 < K) ? ub[k + 1 < K ? k + 1 : 0] : vbR;   // still original here
         const double b = up1 - uk;
         const double p = a * b;
@@ -88,7 +92,7 @@ __device__ __forceinline__ void adj_stage(const double* __restrict__ us, double 
         a = b;
         uk = up1;
         // sliding-window order (see fvm_stage): the next slot starts after this one
-        asm volatile("" : "+v"(a) : "v"(ubk));
+        asm volatile("" : "+v"(a) : "v"(ubk) : "memory");
     }
     // bbar of the last slot goes to the right neighbour's slot 0; -abar of
     // slot 0 to the left neighbour's last slot (lane 0: to the ghost)
