@@ -276,16 +276,19 @@ int launch_classes(pbe_handle* h, int from_initial, int max_steps) {
     h->a.max_steps = max_steps;
     HIP_OK(launch_reset_counter(h->d_queue, kFvmClasses, h->stream));
     HIP_OK(hipEventRecord(h->ev_fork, h->stream));
-    for (int c = 0; c < kFvmClasses; ++c) {
+    // longest grids first: their workgroups should find free SIMDs before the
+    // short classes' persistent workgroups take them
+    for (int c = kFvmClasses - 1; c >= 1; --c) {
         if (h->cls_count[c] == 0) continue;
-        hipStream_t st = c == 0 ? h->stream : h->side[c];
-        if (c != 0) HIP_OK(hipStreamWaitEvent(st, h->ev_fork, 0));
-        HIP_OK(launch_fvm1d_class(c, h->a, h->cls_blocks[c], h->cls_begin[c], h->cls_count[c], h->d_queue + c, st));
-        if (c != 0) {
-            HIP_OK(hipEventRecord(h->ev_join[c], st));
-            HIP_OK(hipStreamWaitEvent(h->stream, h->ev_join[c], 0));
-        }
+        HIP_OK(hipStreamWaitEvent(h->side[c], h->ev_fork, 0));
+        HIP_OK(launch_fvm1d_class(c, h->a, h->cls_blocks[c], h->cls_begin[c], h->cls_count[c], h->d_queue + c,
+                                  h->side[c]));
+        HIP_OK(hipEventRecord(h->ev_join[c], h->side[c]));
     }
+    if (h->cls_count[0] > 0)
+        HIP_OK(launch_fvm1d_class(0, h->a, h->cls_blocks[0], h->cls_begin[0], h->cls_count[0], h->d_queue, h->stream));
+    for (int c = 1; c < kFvmClasses; ++c)
+        if (h->cls_count[c] > 0) HIP_OK(hipStreamWaitEvent(h->stream, h->ev_join[c], 0));
     return PBE_OK;
 }
 
