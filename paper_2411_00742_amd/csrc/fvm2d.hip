@@ -85,6 +85,8 @@ __device__ __forceinline__ double col_feed(ColStage& st, double x, double c, dou
     return out;
 }
 
+constexpr int kColAhead = 8;   // row loads in flight per wave in the column sweep
+
 __global__ __launch_bounds__(64) void k_cols2d(Fvm2dArgs a, int parity) {
     const int b = blockIdx.x;
     const int s = uniform(a.cb_sim[b]);
@@ -107,31 +109,41 @@ __global__ __launch_bounds__(64) void k_cols2d(Fvm2dArgs a, int parity) {
     ColStage s1{0.0, 0.0, 0.0}, s2{0.0, 0.0, 0.0}, s3{0.0, 0.0, 0.0};
     double u0_1 = 0.0, u0_2 = 0.0, u0_3 = 0.0;   // f^n at rows R-1, R-2, R-3
     double m00 = 0.0, m10 = 0.0, m01 = 0.0, m12 = 0.0;
-    for (int R = row0 - 6; R <= row1 + 2; ++R) {
-        double x;
-        if (R < 0) {
-            x = ghost;
-        } else if (R >= n2) {
-            x = 0.0;
-        } else {
-            x = valid ? src[(int64_t)R * n1] : 0.0;
+    // Input rows are loaded kColAhead rows ahead of their use into a ring, so
+    // a wave keeps that many row loads in flight instead of waiting on each
+    // one; rows outside [0, n2) read a clamped in-range row and are replaced
+    // by the ghost (below L2 = 0) or 0 (past L2_max).
+    const int R0 = row0 - 6, R1 = row1 + 2;
+    // (the ring holds the raw loads; the substitution is applied when a row is
+    // consumed, so nothing waits on a load before its turn)
+    auto load_row = [&](int R) -> double { return src[(int64_t)min(max(R, 0), n2 - 1) * n1]; };
+    double ring[kColAhead];
+#pragma unroll
+    for (int j = 0; j < kColAhead; ++j) ring[j] = load_row(R0 + j);
+    for (int Rb = R0; Rb <= R1; Rb += kColAhead) {
+#pragma unroll
+        for (int j = 0; j < kColAhead; ++j) {
+            const int R = Rb + j;
+            if (R > R1) break;
+            const double x = R < 0 ? ghost : (R >= n2 || !valid ? 0.0 : ring[j]);
+            ring[j] = load_row(R + kColAhead);
+            const double v1 = col_feed(s1, x, c, 0.0, 0.0, 1.0, true, R - 1, n2, ghost);
+            const double v2 = col_feed(s2, v1, c, u0_2, 0.75, 0.25, false, R - 2, n2, ghost);
+            const double v3 = col_feed(s3, v2, c, u0_3, 1.0 / 3.0, 2.0 / 3.0, false, R - 3, n2, ghost);
+            const int r = R - 3;
+            if (r >= row0 && r < row1) {
+                if (valid) dst[(int64_t)r * n1] = v3;
+                const double f = valid ? v3 : 0.0;
+                const double L2c = (r + 0.5) * d2;
+                m00 += f;
+                m10 = fma(L1c, f, m10);
+                m01 = fma(L2c, f, m01);
+                m12 = fma(L1c * L2c * L2c, f, m12);
+            }
+            u0_3 = u0_2;
+            u0_2 = u0_1;
+            u0_1 = x;
         }
-        const double v1 = col_feed(s1, x, c, 0.0, 0.0, 1.0, true, R - 1, n2, ghost);
-        const double v2 = col_feed(s2, v1, c, u0_2, 0.75, 0.25, false, R - 2, n2, ghost);
-        const double v3 = col_feed(s3, v2, c, u0_3, 1.0 / 3.0, 2.0 / 3.0, false, R - 3, n2, ghost);
-        const int r = R - 3;
-        if (r >= row0 && r < row1) {
-            if (valid) dst[(int64_t)r * n1] = v3;
-            const double f = valid ? v3 : 0.0;
-            const double L2c = (r + 0.5) * d2;
-            m00 += f;
-            m10 = fma(L1c, f, m10);
-            m01 = fma(L2c, f, m01);
-            m12 = fma(L1c * L2c * L2c, f, m12);
-        }
-        u0_3 = u0_2;
-        u0_2 = u0_1;
-        u0_1 = x;
     }
     const double dA = d1 * d2;
     m00 = wave_sum(m00) * dA;
