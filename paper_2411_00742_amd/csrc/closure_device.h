@@ -40,18 +40,19 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// float -> bfloat16 bits, round to nearest with ties to even (finite inputs)
+// float -> bfloat16 bits, round to nearest with ties to even: the gfx950
+// conversion instruction (v_cvt_pk_bf16_f32, two values per instruction)
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
+    return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
 
-// tanh in fp32 from the hardware base-2 exponential: tanh|x| = (1 - e)/(1 + e), e = exp(-2|x|)
+// tanh in fp32 from the hardware base-2 exponential: tanh|x| = (1 - e)/(1 + e),
+// e = exp(-2|x|), with the hardware reciprocal of 1 + e in [1, 2] (about an ulp;
+// the result is rounded to bfloat16, 2^-9 relative, before it is used)
 __device__ __forceinline__ float tanh32(float x) {
     const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * __builtin_fabsf(x));
-    return __builtin_copysignf((1.0f - e) / (1.0f + e), x);
+    return __builtin_copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
 }
 // tanh in fp64 from exp64 (absolute error ~1e-16)
 __device__ __forceinline__ double tanh64(double x) {
