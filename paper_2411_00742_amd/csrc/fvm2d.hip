@@ -24,8 +24,13 @@ namespace {
 
 using namespace dev;
 
+// The row moves between HBM and registers through LDS: the wave reads and
+// writes the row as 64 consecutive doubles per instruction (element e = lane +
+// 64 i of the right-aligned row), and each lane takes its K consecutive cells
+// from LDS.  Element e sits at (e / K) * P + e % K with P = K rounded up to odd,
+// so the K-strided per-lane reads fall in distinct banks.
 template <int K>
-__device__ __forceinline__ void row_sweep(const Fvm2dArgs& a, int parity, int s, int j) {
+__device__ __forceinline__ void row_sweep(const Fvm2dArgs& a, int parity, int s, int j, double* lds) {
     const int lane = threadIdx.x;
     const int n1 = uniform(a.n1[s]);
     const int pad = 64 * K - n1;
@@ -33,34 +38,51 @@ __device__ __forceinline__ void row_sweep(const Fvm2dArgs& a, int parity, int s,
     g.xb = (double)(lane * K - pad);
     g.gdL = 0.0;   // size-independent growth along each axis
     g.npad = min(max(pad - lane * K, 0), K);
-    const int i0 = lane * K - pad;
     const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
     double* row = a.buf[parity] + o + (int64_t)j * n1;
     // nucleation: row 0 receives half the corner source through its L1 = 0 face
     const double ghost = j == 0 ? uniform(a.gh1[s]) : 0.0;
     const double c = uniform(a.c1[s]);
+    constexpr int P = K | 1;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int e = lane + 64 * i;
+        const int cell = e - pad;   // < n1 always; < 0 in the pad
+        lds[(e / K) * P + e % K] = cell >= 0 ? row[cell] : 0.0;
+    }
+    __syncthreads();
     double u[K];
-    load_cells(u, row, i0, g.npad, 0.0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = lds[lane * P + k];
     (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, c, ghost);
-    store_cells(u, row, i0, g.npad);
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[lane * P + k] = u[k];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int e = lane + 64 * i;
+        const int cell = e - pad;
+        if (cell >= 0) row[cell] = lds[(e / K) * P + e % K];
+    }
 }
 
 template <int KLO>
 __global__ __launch_bounds__(64) void k_rows2d(Fvm2dArgs a, int parity, int begin) {
+    __shared__ double lds[64 * ((KLO + 7) | 1)];
     const int r = begin + (int)blockIdx.x;
     const int s = uniform(a.row_sim[r]);
     if (!uniform(a.active[s])) return;
     const int j = uniform(a.row_j[r]);
     const int K = uniform((a.n1[s] + 63) >> 6);
     switch (K - KLO) {
-        case 0: row_sweep<KLO + 0>(a, parity, s, j); break;
-        case 1: row_sweep<KLO + 1>(a, parity, s, j); break;
-        case 2: row_sweep<KLO + 2>(a, parity, s, j); break;
-        case 3: row_sweep<KLO + 3>(a, parity, s, j); break;
-        case 4: row_sweep<KLO + 4>(a, parity, s, j); break;
-        case 5: row_sweep<KLO + 5>(a, parity, s, j); break;
-        case 6: row_sweep<KLO + 6>(a, parity, s, j); break;
-        case 7: row_sweep<KLO + 7>(a, parity, s, j); break;
+        case 0: row_sweep<KLO + 0>(a, parity, s, j, lds); break;
+        case 1: row_sweep<KLO + 1>(a, parity, s, j, lds); break;
+        case 2: row_sweep<KLO + 2>(a, parity, s, j, lds); break;
+        case 3: row_sweep<KLO + 3>(a, parity, s, j, lds); break;
+        case 4: row_sweep<KLO + 4>(a, parity, s, j, lds); break;
+        case 5: row_sweep<KLO + 5>(a, parity, s, j, lds); break;
+        case 6: row_sweep<KLO + 6>(a, parity, s, j, lds); break;
+        case 7: row_sweep<KLO + 7>(a, parity, s, j, lds); break;
         default: break;
     }
 }
