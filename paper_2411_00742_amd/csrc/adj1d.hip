@@ -326,7 +326,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             }
 
             // solute balance: Phi's output f^m also feeds C^m = C^{m-1} - alpha (mu3(f^m) - mu3(f^{m-1}))
-            double ub[K], l0[K];
+            // ub in registers; the direct (identity) part of the step's adjoint,
+            // l0, waits in LDS (slot k of this lane at l0s[k * 64 + lane]) while
+            // the three stage adjoints run, which keeps their registers free
+            double ub[K];
+            double* l0s = lds + 3 * K * 64;
             {
                 LaneGeom g4 = g;
                 asm volatile("" : "+v"(g4.xb));
@@ -335,14 +339,14 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     const double L = fmax(g4.xb + ((double)k + 0.5), 0.0) * dL;
                     const double lp = lam[k] - p.alpha * lamC * (L * L * L * dL);
                     ub[k] = (2.0 / 3.0) * lp;   // vbar of stage 3
-                    l0[k] = (1.0 / 3.0) * lp;
+                    l0s[k * 64 + lane] = (1.0 / 3.0) * lp;
                 }
             }
             double cbar = 0.0, gbar = 0.0;
             adj_stage<K>(lds + 2 * K * 64, ub, g, c, ghost, lane, cbar, gbar, gam, dL);   // ub = adjoint of u2
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                l0[k] = fma(0.75, ub[k], l0[k]);
+                l0s[k * 64 + lane] = fma(0.75, ub[k], l0s[k * 64 + lane]);
                 ub[k] = 0.25 * ub[k];
             }
             adj_stage<K>(lds + 1 * K * 64, ub, g, c, ghost, lane, cbar, gbar, gam, dL);   // ub = adjoint of u1
@@ -352,7 +356,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 asm volatile("" : "+v"(g5.xb));
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const double l = l0[k] + ub[k];
+                    const double l = l0s[k * 64 + lane] + ub[k];
                     const bool padk = k < g5.npad;   // pad slots were set to the ghost at the step start
                     const double L = fmax(g5.xb + ((double)k + 0.5), 0.0) * dL;
                     gbar += padk ? l : 0.0;
@@ -394,9 +398,9 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 const double dGdS = q.g * r.G0 / r.S;
                 const double dBdS = q.b * r.B / r.S;
                 lamC += (G0b * dGdS + Bb * dBdS) / Csat;
-                gk[0] += G0b * 1e6 * exp64(q.g * r.lnS) * r.arrG;
+                gk[0] += G0b * 1e6 * r.Sg * r.arrG;
                 gk[1] += G0b * r.G0 * r.lnS;
-                gk[2] += Bb * exp64(q.b * r.lnS) * r.arrB;
+                gk[2] += Bb * r.Sb * r.arrB;
                 gk[3] += Bb * r.B * r.lnS;
             }
             if (CL != kClosureNone && fb && lane == 0) {
@@ -421,8 +425,9 @@ constexpr int adj_waves_per_simd(int klo) { return klo == 1 ? 2 : 1; }
 
 template <int KLO, int CL>
 __global__ __launch_bounds__(64, adj_waves_per_simd(KLO)) void k_adj1d(Adj1dArgs A, int cls_begin, int cls_count, int32_t* queue) {
-    // the three SSP-RK3 stage input states of the step being reversed (each lane owns its column)
-    __shared__ double lds[3 * (KLO + 7) * 64];
+    // the three SSP-RK3 stage input states of the step being reversed and the
+    // direct part of its adjoint (each lane owns its column)
+    __shared__ double lds[4 * (KLO + 7) * 64];
     for (;;) {
         const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
         const int idx = __builtin_amdgcn_readfirstlane(ticket);

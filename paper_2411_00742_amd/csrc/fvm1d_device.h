@@ -148,13 +148,14 @@ __device__ __forceinline__ double solubility(const Process& p, double T) {
 // Rates at the current concentration.  S = C/Csat - 1; growth G0 (um/s, at
 // L = 0) and nucleation B act only for S > 0.  S^g and S^b share one log.
 struct Rates {
-    double G0, B, S, lnS, arrG, arrB;   // lnS and the Arrhenius factors are kept for the adjoint
+    double G0, B, S, lnS, arrG, arrB;   // lnS and the Arrhenius factors are kept for the adjoint,
+    double Sg, Sb;                      // and so are S^g and S^b
 };
 __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& q, double C, double t) {
     Rates r;
     const double T = temperature(q, t);
     r.S = div_fast(C, solubility(p, T)) - 1.0;
-    r.G0 = 0.0; r.B = 0.0; r.lnS = 0.0; r.arrG = 1.0; r.arrB = 1.0;
+    r.G0 = 0.0; r.B = 0.0; r.lnS = 0.0; r.arrG = 1.0; r.arrB = 1.0; r.Sg = 0.0; r.Sb = 0.0;
     if (r.S > 0.0) {
         r.lnS = log64(r.S);
         if (p.law == PBE_LAW_ARRHENIUS) {
@@ -162,8 +163,10 @@ __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& 
             r.arrG = exp64(-q.Eg * iT);
             r.arrB = exp64(-q.Eb * iT);
         }
-        r.G0 = 1e6 * q.kg * exp64(q.g * r.lnS) * r.arrG;
-        r.B = q.kb * exp64(q.b * r.lnS) * r.arrB;
+        r.Sg = exp64(q.g * r.lnS);
+        r.Sb = exp64(q.b * r.lnS);
+        r.G0 = 1e6 * q.kg * r.Sg * r.arrG;
+        r.B = q.kb * r.Sb * r.arrB;
     }
     r.G0 = uniform(r.G0);
     r.B = uniform(r.B);
