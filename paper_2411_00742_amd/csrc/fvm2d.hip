@@ -4,13 +4,16 @@
 //
 // One global step = three launches (captured in a graph by the host):
 //   k_rows2d  L1 sweep: one wavefront per row, the row in registers exactly as
-//             the 1D kernel holds a simulation (same stage code), in place;
+//             the 1D kernel holds a simulation (same stage code), in place; the
+//             row passes through LDS on its way in and out so that every
+//             global access is a contiguous 512-byte wave access;
 //   k_cols2d  L2 sweep: a wavefront owns 64 adjacent columns and a segment of
 //             rows; each lane marches down its column with the three SSP-RK3
 //             stages pipelined in registers (stage s lags s rows), so every
 //             load and store is a coalesced 512-byte row segment and no lane
 //             talks to another.  Segments start 6 rows early (the stencil halo
-//             of three stages); the sweep reads one buffer and writes the other.
+//             of three stages); the sweep reads one buffer and writes the other,
+//             with eight row loads in flight per wave.
 //             It also sums the moments of the swept state per block;
 //   k_final2d one wavefront per simulation: reduces the block moments in a fixed
 //             order, applies the solute balance (Eq. (9) with mu_{1,2}), records
