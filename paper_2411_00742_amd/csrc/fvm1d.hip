@@ -161,10 +161,12 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
 // K instead of the global maximum.  The classes run concurrently, each over
 // its own work queue.
 // waves per SIMD each class is held to (the register budget follows: 4 -> 128,
-// 3 -> 168, 2 -> 256 VGPRs); the 25-32 class needs the whole budget, and the
-// closure's network takes one step of occupancy more
+// 3 -> 168, 2 -> 256 VGPRs); the 25-32 class needs the whole budget; the
+// closure kernels hold the 1-8 class at 4 (a few spills, but one wave per
+// simulation of a 4096-simulation batch fits the device at once) and the
+// 9-16 class at 2
 constexpr int fvm_waves_per_simd(int klo, int cl) {
-    return cl != 0 ? (klo == 1 ? 3 : 2) : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
+    return cl != 0 ? (klo == 1 ? 4 : 2) : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
 }
 
 // run simulation s with its K (uniform) in [KA, KHI]: a chain of scalar branches
