@@ -121,23 +121,29 @@ Kinetics<R> load_kinetics(const double* par) {
     return k;
 }
 
-// Linear cooling from T0 to T1 over t_ramp seconds, then held at T1.
-double temperature(const double* par, double t) {
+// Linear cooling from T0 to T1 over t_ramp seconds, then held at T1.  The
+// time may carry derivatives (the step size, and so the time reached, depends
+// on the parameters wherever the CFL limit sets the step).
+template <class R>
+R temperature(const double* par, const R& t) {
     const double tr = par[K_TRAMP];
-    const double frac = tr > 0.0 ? std::min(t, tr) / tr : 1.0;
+    const R frac = (tr > 0.0 && val(t) < tr) ? t / tr : R(1.0);
     return par[K_T0] + (par[K_T1] - par[K_T0]) * frac;
 }
+double temperature(const double* par, double t) { return temperature<double>(par, t); }
 
 // Solubility: linear, or the exponential form of App. A Eq. (A.1).
-double solubility(const ref_process* p, double T) {
-    return p->sol_law == REF_SOL_EXP ? p->cs0 * std::exp(p->cs1 * T) : p->cs0 + p->cs1 * T;
+template <class R>
+R solubility(const ref_process* p, const R& T) {
+    return p->sol_law == REF_SOL_EXP ? p->cs0 * exp(p->cs1 * T) : p->cs0 + p->cs1 * T;
 }
+double solubility(const ref_process* p, double T) { return solubility<double>(p, T); }
 
 // Relative supersaturation S = C/Csat - 1, and its positive part: the growth
 // and nucleation laws act only while the solution is supersaturated
 // (App. A, the condition stated under Eq. (A.2)).
-template <class R>
-R supersaturation_pos(R C, double Csat) {
+template <class R, class Q>
+R supersaturation_pos(R C, const Q& Csat) {
     R S = C / Csat - 1.0;
     if (val(S) > 0.0) return S;
     return R(0.0);
@@ -146,15 +152,15 @@ R supersaturation_pos(R C, double Csat) {
 // Growth rate G0 [um/s] at L = 0 along axis 1, the second axis rate G2, and
 // the nucleation rate B [#/(m^3 s)].  Power law, or the power law times the
 // Arrhenius temperature factor of App. A Eq. (A.2).
-template <class R>
-void rate_laws(int law, const Kinetics<R>& k, double T, R Sp, R& G0, R& G2, R& B) {
+template <class R, class Q>
+void rate_laws(int law, const Kinetics<R>& k, const Q& T, R Sp, R& G0, R& G2, R& B) {
     G0 = 1e6 * k.kg * power(Sp, k.g);
     G2 = 1e6 * k.kg2 * power(Sp, k.g2);
     B = k.kb * power(Sp, k.b);
     if (law == REF_LAW_ARRHENIUS) {
-        G0 = G0 * std::exp(-k.Eg / (T + 273.15));
-        G2 = G2 * std::exp(-k.Eg / (T + 273.15));
-        B = B * std::exp(-k.Eb / (T + 273.15));
+        G0 = G0 * exp(-k.Eg / (T + 273.15));
+        G2 = G2 * exp(-k.Eg / (T + 273.15));
+        B = B * exp(-k.Eb / (T + 273.15));
     }
 }
 
@@ -166,7 +172,8 @@ constexpr int MH = REF_MLP_H;
 constexpr int OFF_W1 = 0, OFF_B1 = 3 * MH, OFF_W2 = 4 * MH, OFF_B2 = 4 * MH + MH * MH, OFF_W3 = 5 * MH + MH * MH,
               OFF_B3 = 7 * MH + MH * MH;
 static_assert(OFF_B3 + 2 == REF_MLP_NW, "closure weight count");
-enum { C_IN_SHIFT = 0, C_IN_SCALE = 3, C_OUT_SHIFT = 6, C_OUT_SCALE = 8, C_LO = 10, C_HI = 13, C_SMIN = 16 };
+enum { C_IN_SHIFT = 0, C_IN_SCALE = 3, C_OUT_SHIFT = 6, C_OUT_SCALE = 8, C_LO = 10, C_HI = 13, C_SMIN = 16,
+       C_LNG0_MAX = 17 };
 
 // float -> bfloat16 -> float, round to nearest with ties to even on the 16
 // discarded bits of the IEEE single pattern (finite inputs)
@@ -246,10 +253,10 @@ void net_forward(const Net<R>& n, const R z[3], R y[2]) {
 // Closure rates at supersaturation S (not clipped), temperature T and second
 // moment mu2.  Returns true when the plain power law was used instead.
 template <class R>
-bool closure_rates(const Net<R>& n, const Kinetics<R>& k, const R& S, double T, const R& mu2, R& G0, R& B) {
+bool closure_rates(const Net<R>& n, const Kinetics<R>& k, const R& S, const R& T, const R& mu2, R& G0, R& B) {
     const double* c = n.c;
     bool inside = val(S) > c[C_SMIN] && val(mu2) > 0.0;
-    R x[3] = {S, R(T), R(0.0)};
+    R x[3] = {S, T, R(0.0)};
     if (inside) x[2] = log(mu2) / std::log(10.0);
     for (int q = 0; q < 3 && inside; ++q) inside = val(x[q]) >= c[C_LO + q] && val(x[q]) <= c[C_HI + q];
     if (!inside) {
@@ -261,7 +268,12 @@ bool closure_rates(const Net<R>& n, const Kinetics<R>& k, const R& S, double T, 
     R z[3], y[2];
     for (int q = 0; q < 3; ++q) z[q] = (x[q] - c[C_IN_SHIFT + q]) * c[C_IN_SCALE + q];
     net_forward(n, z, y);
-    G0 = exp(c[C_OUT_SHIFT] + c[C_OUT_SCALE] * y[0]);
+    // the network's growth rate is trusted up to exp(lnG0_max): beyond it the
+    // log-rate is held at that bound (zero derivative), which also bounds the
+    // number of CFL-limited steps a solve can take
+    R lnG = c[C_OUT_SHIFT] + c[C_OUT_SCALE] * y[0];
+    if (val(lnG) > c[C_LNG0_MAX]) lnG = R(c[C_LNG0_MAX]);
+    G0 = exp(lnG);
     B = exp(c[C_OUT_SHIFT + 1] + c[C_OUT_SCALE + 1] * y[1]);
     return false;
 }
@@ -296,7 +308,7 @@ R limited_slope(const R& a, const R& b) {
 // kappa = 1 - vel_j dt/dL for the one-step update of Eq. (8).
 template <class R>
 void face_fluxes(const std::vector<R>& u, int n, double dL, const R& G0, const R& gamma, const R& inflow,
-                 int scheme, double dt, std::vector<R>& F) {
+                 int scheme, const R& dt, std::vector<R>& F) {
     std::vector<R> e(n + 3);           // e[i + 2] is cell i, i = -2..n
     e[0] = inflow;
     e[1] = inflow;
@@ -326,7 +338,7 @@ void flux_divergence(const std::vector<R>& F, int n, double dL, std::vector<R>& 
 // `out` accumulates dt * (stage-weighted flux through the last face).
 template <class R>
 void advance_line(std::vector<R>& f, int n, double dL, const R& G0, const R& gamma, const R& inflow,
-                  int scheme, double dt, R& out) {
+                  int scheme, const R& dt, R& out) {
     std::vector<R> F(n + 1), rhs(n);
     if (scheme == REF_SCHEME_LW_TVD) {
         face_fluxes(f, n, dL, G0, gamma, inflow, scheme, dt, F);
@@ -370,24 +382,34 @@ R moment1d(const std::vector<R>& f, int n, double dL, int k) {
 
 bool finite(double x) { return std::isfinite(x); }
 
+// Which limit sets a step: the CFL bound of SI Eq. (S3), the cap dt_max, or
+// the clamp that lands the step on the next sample time (or t_end).
+enum { DT_CFL = 0, DT_CAP = 1, DT_LAND = 2 };
+
 // Step size: CFL limit nu*dL/max G (SI Eq. (S3)), capped at dt_max, clamped so
-// that the step lands exactly on the next sample time (or t_end).  Returns
-// true when the step lands on t_next.
-bool choose_dt(double cfl_limit, double dt_max, double t, double t_next, double t_end, const double* replay,
-               int n_replay, int step, double* dt) {
+// that the step lands exactly on the next sample time (or t_end).  A replayed
+// step size counts as a constant (the cap).  Returns which limit applies.
+int choose_dt(double cfl_limit, double dt_max, double t, double t_next, double t_end, const double* replay,
+              int n_replay, int step, double* dt) {
     double d;
+    int kind;
     if (replay && step < n_replay) {
         d = replay[step];
+        kind = DT_CAP;
+    } else if (cfl_limit < dt_max) {
+        d = cfl_limit;
+        kind = DT_CFL;
     } else {
-        d = std::min(cfl_limit, dt_max);
+        d = dt_max;
+        kind = DT_CAP;
     }
     const double rem = t_next - t;
     if (d >= rem - 1e-12 * t_end) {
         *dt = rem;
-        return true;
+        return DT_LAND;
     }
     *dt = d;
-    return false;
+    return kind;
 }
 
 // ---------------------------------------------------------------------------
@@ -409,7 +431,12 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
     std::vector<R> f(n);
     for (int i = 0; i < n; ++i) f[i] = R(s->f0[i]);
     R C(s->C0);
-    double t = 0.0;
+    // Time carries derivatives: a CFL-limited step (SI Eq. (S3)) depends on
+    // the growth rate, so the time reached after it, the temperature of the
+    // cooling ramp and the length of a step that lands on a sample time all
+    // depend on the parameters.  With a replayed schedule every step is a
+    // constant and so is the time.
+    R t(0.0);
     R mu3_old = moment1d(f, n, dL, 3);
     R out(0.0);
     int step = 0, next = 0, status = REF_SIM_OK;
@@ -428,9 +455,9 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
             for (int i = 0; i < n; ++i) (*tan_out->f_samples)[(size_t)q * n + i] = f[i];
     };
 
-    while (t < p->t_end && step < max_steps) {
-        const double T = temperature(s->par, t);
-        const double Csat = solubility(p, T);
+    while (val(t) < p->t_end && step < max_steps) {
+        const R T = temperature<R>(s->par, t);
+        const R Csat = solubility<R>(p, T);
         const R Sp = supersaturation_pos(C, Csat);
         R G0, G2, B;
         if (p->law == REF_LAW_MLP) {
@@ -439,13 +466,24 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
         } else {
             rate_laws(p->law, k, T, Sp, G0, G2, B);
         }
+        // rates handed in from elsewhere (checks the finite-volume part on its own)
+        if (s->G0_replay && s->B_replay && step < s->n_rates_replay) {
+            G0 = R(s->G0_replay[step]);
+            B = R(s->B_replay[step]);
+        }
 
         const double t_next = next < s->n_samples ? s->t_samples[next] : p->t_end;
         const double Gmax = val(G0) * (1.0 + val(k.gamma) * s->L_max);
         const double cfl_limit = Gmax > 0.0 ? p->cfl * dL / Gmax : std::numeric_limits<double>::infinity();
-        double dt;
-        const bool hit = choose_dt(cfl_limit, p->dt_max, t, t_next, p->t_end, s->dt_replay, s->n_replay, step, &dt);
-        if (s->dt_log) s->dt_log[step] = dt;
+        double dtv;
+        const int kind = choose_dt(cfl_limit, p->dt_max, val(t), t_next, p->t_end, s->dt_replay, s->n_replay, step,
+                                   &dtv);
+        const bool hit = kind == DT_LAND;
+        // the step as a function of the state and parameters, in the branch the values select
+        R dt(dtv);
+        if (kind == DT_CFL) dt = with_value(p->cfl * dL / (G0 * (1.0 + k.gamma * s->L_max)), dtv);
+        if (kind == DT_LAND) dt = with_value(t_next - t, dtv);
+        if (s->dt_log) s->dt_log[step] = dtv;
         if (s->G0_log) s->G0_log[step] = val(G0);
         if (s->B_log) s->B_log[step] = val(B);
 
@@ -459,14 +497,14 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
         C = C - p->alpha * (mu3 - mu3_old);
         mu3_old = mu3;
 
-        t = hit ? t_next : t + dt;
+        t = hit ? R(t_next) : t + dt;
         ++step;
         if (!finite(val(C)) || !finite(val(mu3))) {
             status |= REF_SIM_NONFINITE;
             break;
         }
         if (hit) {
-            while (next < s->n_samples && s->t_samples[next] <= t) record(next++);
+            while (next < s->n_samples && s->t_samples[next] <= val(t)) record(next++);
         }
     }
     const double mu0 = val(moment1d(f, n, dL, 0));
@@ -475,7 +513,7 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
     if (s->steps) *s->steps = step;
     if (s->status) *s->status = status;
     if (s->C_final) *s->C_final = val(C);
-    if (s->t_final) *s->t_final = t;
+    if (s->t_final) *s->t_final = val(t);
     if (s->outflow) *s->outflow = val(out);
     return 0;
 }
@@ -532,7 +570,7 @@ int solve2d_impl(const ref_process* p, ref_sim2d* s) {
         if (G1 > 0.0) lim = std::min(lim, d1 / G1);
         if (G2 > 0.0) lim = std::min(lim, d2 / G2);
         double dt;
-        const bool hit = choose_dt(p->cfl * lim, p->dt_max, t, t_next, p->t_end, nullptr, 0, step, &dt);
+        const bool hit = choose_dt(p->cfl * lim, p->dt_max, t, t_next, p->t_end, nullptr, 0, step, &dt) == DT_LAND;
         if (s->dt_log) s->dt_log[step] = dt;
 
         // sweep along L1: every row j is a 1D line of n1 cells
@@ -703,27 +741,27 @@ int ref_solve1d_batch(const ref_process* p, ref_sim1d* sims, int32_t n_sims, int
     return run_pool(n_sims, n_threads, [&](int i) { ref_solve1d(p, &sims[i]); });
 }
 
-int ref_tangent1d(const ref_process* p, ref_sim1d* s, double* dF, double* dM, double* dC) {
+// Primal run of one simulation that records its step sizes (for a replay).
+static std::vector<double> primal_schedule(const ref_process* p, const ref_sim1d* s, const Net<double>* net) {
+    const int cap = s->max_steps > 0 ? std::min(s->max_steps, 2000000) : 2000000;
+    std::vector<double> dts(cap);
+    int steps = 0;
+    ref_sim1d s0 = *s;
+    s0.f_samples = nullptr; s0.mom = nullptr; s0.C = nullptr; s0.f_final = nullptr;
+    s0.G0_log = nullptr; s0.B_log = nullptr; s0.outflow = nullptr;
+    s0.C_final = nullptr; s0.t_final = nullptr; s0.status = nullptr;
+    s0.dt_log = dts.data();
+    s0.steps = &steps;
+    s0.max_steps = cap;
+    solve1d_impl<double>(p, &s0, load_kinetics<double>(s0.par), nullptr, net);
+    dts.resize(steps);
+    return dts;
+}
+
+int ref_tangent1d(const ref_process* p, ref_sim1d* s, int32_t dt_mode, double* dF, double* dM, double* dC) {
     typedef Dual<REF_NTAN> D;
     if (!p || !s || s->n < 1 || p->law == REF_LAW_MLP) return -1;
-    // primal run: records the step-size schedule that the tangent run replays
-    const int cap = s->max_steps > 0 ? s->max_steps : 10000000;
-    std::vector<double> dts;
-    int steps = 0;
-    {
-        ref_sim1d s0 = *s;
-        s0.f_samples = nullptr; s0.mom = nullptr; s0.C = nullptr; s0.f_final = nullptr;
-        s0.G0_log = nullptr; s0.B_log = nullptr; s0.outflow = nullptr;
-        s0.C_final = nullptr; s0.t_final = nullptr; s0.status = nullptr;
-        // the schedule length is bounded by the cap; probe with a generous buffer
-        const int probe = std::min(cap, 2000000);
-        dts.resize(probe);
-        s0.dt_log = dts.data();
-        s0.steps = &steps;
-        s0.max_steps = probe;
-        solve1d_impl<double>(p, &s0, load_kinetics<double>(s0.par), nullptr);
-        dts.resize(steps);
-    }
+    if (dt_mode != REF_DT_DIFF && dt_mode != REF_DT_FROZEN) return -1;
     Kinetics<D> k = load_kinetics<D>(s->par);
     k.kg.d[0] = 1.0; k.g.d[1] = 1.0; k.kb.d[2] = 1.0; k.b.d[3] = 1.0; k.gamma.d[4] = 1.0;
     std::vector<D> tf((size_t)s->n_samples * s->n), tm((size_t)s->n_samples * 4), tc(s->n_samples);
@@ -732,9 +770,14 @@ int ref_tangent1d(const ref_process* p, ref_sim1d* s, double* dF, double* dM, do
     tan.mom = &tm;
     tan.C = &tc;
     ref_sim1d s1 = *s;
-    s1.dt_replay = dts.data();
-    s1.n_replay = steps;
-    s1.max_steps = steps;
+    std::vector<double> dts;
+    if (dt_mode == REF_DT_FROZEN) {
+        // the step-size schedule of the primal run, replayed as constants
+        dts = primal_schedule(p, s, nullptr);
+        s1.dt_replay = dts.data();
+        s1.n_replay = (int)dts.size();
+        s1.max_steps = (int)dts.size();
+    }
     solve1d_impl<D>(p, &s1, k, &tan);
     for (int q = 0; q < s->n_samples; ++q) {
         for (int d = 0; d < REF_NTAN; ++d) {
@@ -824,24 +867,11 @@ int ref_mlp_vjp(const float* blob, int32_t precision, int32_t n, const double* z
     return 0;
 }
 
-int ref_tangent1d_mlp(const ref_process* p, ref_sim1d* s, const double* v, double* dF, double* dM, double* dC) {
+int ref_tangent1d_mlp(const ref_process* p, ref_sim1d* s, int32_t dt_mode, const double* v, double* dF, double* dM,
+                      double* dC) {
     typedef Dual<2> D;
     if (!p || !s || s->n < 1 || p->law != REF_LAW_MLP || !p->mlp || !v) return -1;
-    const Net<double> net0 = load_net<double>(p->mlp, p->mlp_precision, nullptr, -1);
-    const int cap = s->max_steps > 0 ? s->max_steps : 2000000;
-    std::vector<double> dts(std::min(cap, 2000000));
-    int steps = 0;
-    {
-        ref_sim1d s0 = *s;
-        s0.f_samples = nullptr; s0.mom = nullptr; s0.C = nullptr; s0.f_final = nullptr;
-        s0.G0_log = nullptr; s0.B_log = nullptr; s0.outflow = nullptr;
-        s0.C_final = nullptr; s0.t_final = nullptr; s0.status = nullptr;
-        s0.dt_log = dts.data();
-        s0.steps = &steps;
-        s0.max_steps = (int)dts.size();
-        solve1d_impl<double>(p, &s0, load_kinetics<double>(s0.par), nullptr, &net0);
-        dts.resize(steps);
-    }
+    if (dt_mode != REF_DT_DIFF && dt_mode != REF_DT_FROZEN) return -1;
     const Net<D> net = load_net<D>(p->mlp, p->mlp_precision, v, 0);
     Kinetics<D> k = load_kinetics<D>(s->par);
     k.gamma.d[1] = 1.0;
@@ -851,9 +881,14 @@ int ref_tangent1d_mlp(const ref_process* p, ref_sim1d* s, const double* v, doubl
     tan.mom = &tm;
     tan.C = &tc;
     ref_sim1d s1 = *s;
-    s1.dt_replay = dts.data();
-    s1.n_replay = steps;
-    s1.max_steps = steps;
+    std::vector<double> dts;
+    if (dt_mode == REF_DT_FROZEN) {
+        const Net<double> net0 = load_net<double>(p->mlp, p->mlp_precision, nullptr, -1);
+        dts = primal_schedule(p, s, &net0);
+        s1.dt_replay = dts.data();
+        s1.n_replay = (int)dts.size();
+        s1.max_steps = (int)dts.size();
+    }
     solve1d_impl<D>(p, &s1, k, &tan, &net);
     for (int q = 0; q < s->n_samples; ++q)
         for (int d = 0; d < 2; ++d) {

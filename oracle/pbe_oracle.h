@@ -20,7 +20,8 @@
  *   - the discrete solute mass balance, Sec. 2.1 Eq. (9);
  *   - moments, SI S1.2 Eq. (S5), and the method-of-moments ODEs, Eq. (S4);
  *   - forward-mode derivatives (dual numbers), SI S2.1-S2.2, used as the
- *     reference gradient with the time-step schedule held fixed.
+ *     reference gradient, with the step sizes differentiated in the branch
+ *     the primal run takes (or, on request, held at the primal run's values).
  *
  * Units: L um, t s, T degC, f #/(m^3 um^d), G um/s, B #/(m^3 s), C g/g.
  * Kinetic parameter kg is in m/s and is scaled by 1e6 to um/s.
@@ -49,11 +50,11 @@ enum { REF_SIM_OK = 0, REF_SIM_NONFINITE = 1, REF_SIM_OUTFLOW = 2, REF_SIM_FALLB
 /* Learned closure (Sec. 4.2, Fig. 5a: a network replaces the advection-rate
  * computation of the loop in Fig. 1).  Blob of REF_MLP_NBLOB floats:
  *   W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]        (REF_MLP_NW weights)
- *   in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
+ *   in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min lnG0_max
  * Inputs x = (S, T [degC], log10 mu_2) with S = C/Csat - 1, normalised as
  * z_k = (x_k - in_shift_k) * in_scale_k;  h1 = tanh(W1 z + b1),
- * h2 = tanh(W2 h1 + b2), y = W3 h2 + b3;  ln G0 = out_shift_0 + out_scale_0 y_0
- * (G0 in um/s) and ln B = out_shift_1 + out_scale_1 y_1.  Where S <= s_min,
+ * h2 = tanh(W2 h1 + b2), y = W3 h2 + b3;  ln G0 = min(out_shift_0 + out_scale_0 y_0,
+ * lnG0_max) (G0 in um/s) and ln B = out_shift_1 + out_scale_1 y_1.  Where S <= s_min,
  * mu_2 <= 0 or some x_k lies outside [lo_k, hi_k], the plain power law with the
  * simulation's (kg, g, kb, b) is used instead and REF_SIM_FALLBACK is set.
  * Precision REF_MLP_FP64: all in double.  REF_MLP_BF16: z, the weights and the
@@ -64,7 +65,7 @@ enum { REF_SIM_OK = 0, REF_SIM_NONFINITE = 1, REF_SIM_OUTFLOW = 2, REF_SIM_FALLB
  * unchanged, with tanh' = 1 - t^2 at the float value t. */
 #define REF_MLP_H 64
 #define REF_MLP_NW 4546
-#define REF_MLP_NC 17
+#define REF_MLP_NC 18
 #define REF_MLP_NBLOB (REF_MLP_NW + REF_MLP_NC)
 enum { REF_MLP_BF16 = 0, REF_MLP_FP64 = 1 };
 
@@ -82,12 +83,14 @@ typedef struct {
     int32_t n_samples;
     int32_t max_steps;        /* stop after this many steps (state is then "current") */
     int32_t n_replay;         /* >0: use dt_replay[0..n_replay) as the step sizes */
+    int32_t n_rates_replay;   /* >0: use G0_replay, B_replay[0..n_rates_replay) instead of the rate law */
     double L_max;
     double C0;
     const double *f0;         /* [n] */
     const double *par;        /* [REF_NPAR] */
     const double *t_samples;  /* [n_samples] ascending in (0, t_end] */
     const double *dt_replay;
+    const double *G0_replay, *B_replay;
     /* outputs */
     double *f_samples;        /* [n_samples][n] */
     double *mom;              /* [n_samples][4]  mu_0..mu_3 */
@@ -122,10 +125,17 @@ int ref_solve1d(const ref_process *p, ref_sim1d *s);
  * Returns the number of threads used. */
 int ref_solve1d_batch(const ref_process *p, ref_sim1d *sims, int32_t n_sims, int32_t n_threads);
 
-/* Forward-mode derivatives of the recorded samples w.r.t. (kg, g, kb, b, gamma)
- * with the step-size schedule of the primal run held fixed.
+/* Step sizes in the derivatives: REF_DT_DIFF differentiates each step in the
+ * branch its values select (a CFL-limited step nu*dL/(G0 (1 + gamma L_max))
+ * depends on the rates and gamma, a step that lands on a sample time on the
+ * time reached; the time, the cooling ramp's temperature and so the rates
+ * carry that dependence); the step count and the branches are those of the
+ * primal run.  REF_DT_FROZEN replays the primal run's step sizes as constants. */
+enum { REF_DT_DIFF = 0, REF_DT_FROZEN = 1 };
+
+/* Forward-mode derivatives of the recorded samples w.r.t. (kg, g, kb, b, gamma).
  * dF [n_samples][n][5], dM [n_samples][4][5], dC [n_samples][5] (each may be NULL). */
-int ref_tangent1d(const ref_process *p, ref_sim1d *s, double *dF, double *dM, double *dC);
+int ref_tangent1d(const ref_process *p, ref_sim1d *s, int32_t dt_mode, double *dF, double *dM, double *dC);
 
 /* (double)(bfloat16)(float)x with round-to-nearest-even at both steps. */
 double ref_bf16(double x);
@@ -136,9 +146,10 @@ int ref_mlp_forward(const float *blob, int32_t precision, int32_t n, const doubl
  * z[n][3]: gw[REF_MLP_NW], same order as the blob's weights. */
 int ref_mlp_vjp(const float *blob, int32_t precision, int32_t n, const double *z, const double *ybar, double *gw);
 /* Learned-closure solve: forward-mode derivatives along the weight direction
- * v[REF_MLP_NW] (tangent 0) and along gamma (tangent 1), step schedule of the
- * primal run held fixed.  dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
-int ref_tangent1d_mlp(const ref_process *p, ref_sim1d *s, const double *v, double *dF, double *dM, double *dC);
+ * v[REF_MLP_NW] (tangent 0) and along gamma (tangent 1), steps as dt_mode says.
+ * dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
+int ref_tangent1d_mlp(const ref_process *p, ref_sim1d *s, int32_t dt_mode, const double *v, double *dF, double *dM,
+                      double *dC);
 
 int ref_solve2d(const ref_process *p, ref_sim2d *s);
 int ref_solve2d_batch(const ref_process *p, ref_sim2d *sims, int32_t n_sims, int32_t n_threads);

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libpbe_oracle.so")
 SOURCES = [os.path.join(HERE, "pbe_oracle.cpp")]
 NPAR = 12
 NTAN = 5
+DT_DIFF, DT_FROZEN = 0, 1
+MLP_NC = 18
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -44,8 +46,10 @@ class Process(C.Structure):
 
 class Sim1D(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_samples", C.c_int32), ("max_steps", C.c_int32), ("n_replay", C.c_int32),
+                ("n_rates_replay", C.c_int32),
                 ("L_max", C.c_double), ("C0", C.c_double),
                 ("f0", _dp), ("par", _dp), ("t_samples", _dp), ("dt_replay", _dp),
+                ("G0_replay", _dp), ("B_replay", _dp),
                 ("f_samples", _dp), ("mom", _dp), ("C", _dp), ("f_final", _dp), ("dt_log", _dp),
                 ("G0_log", _dp), ("B_log", _dp),
                 ("steps", _ip), ("status", _ip),
@@ -76,7 +80,7 @@ def lib():
         L.ref_limited_slope.argtypes = [C.c_double, C.c_double]
         L.ref_solve1d.argtypes = [C.POINTER(Process), C.POINTER(Sim1D)]
         L.ref_solve1d_batch.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, C.c_int32]
-        L.ref_tangent1d.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), _dp, _dp, _dp]
+        L.ref_tangent1d.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp]
         L.ref_solve2d.argtypes = [C.POINTER(Process), C.POINTER(Sim2D)]
         L.ref_solve2d_batch.argtypes = [C.POINTER(Process), C.POINTER(Sim2D), C.c_int32, C.c_int32]
         L.ref_mom1d.argtypes = [C.POINTER(Process), _dp, C.c_double, _dp, C.c_int32, _dp, C.c_double, C.c_double,
@@ -88,7 +92,7 @@ def lib():
         _fp = C.POINTER(C.c_float)
         L.ref_mlp_forward.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
         L.ref_mlp_vjp.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
-        L.ref_tangent1d_mlp.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), _dp, _dp, _dp, _dp]
+        L.ref_tangent1d_mlp.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -129,13 +133,19 @@ def dual_example(x1: float, x2: float) -> np.ndarray:
 class _Sim1DBuffers:
     """Owns the numpy arrays a Sim1D struct points into."""
 
-    def __init__(self, prob, s, record_f, max_steps, dt_replay, log_steps):
+    def __init__(self, prob, s, record_f, max_steps, dt_replay, log_steps, rates_replay=None):
         n = int(prob.n_cells[s])
         ns = len(prob.t_samples)
         self.f0 = np.ascontiguousarray(prob.f0_of(s), dtype=np.float64)
         self.par = np.ascontiguousarray(prob.par[s], dtype=np.float64)
         self.ts = np.ascontiguousarray(prob.t_samples, dtype=np.float64)
         self.replay = None if dt_replay is None else np.ascontiguousarray(dt_replay, dtype=np.float64)
+        if rates_replay is None:
+            self.G0r = self.Br = None
+        else:
+            self.G0r = np.ascontiguousarray(rates_replay[0], dtype=np.float64)
+            self.Br = np.ascontiguousarray(rates_replay[1], dtype=np.float64)
+            assert self.G0r.shape == self.Br.shape
         self.f_samples = np.zeros((ns, n)) if record_f else None
         self.mom = np.zeros((ns, 4))
         self.C = np.zeros(ns)
@@ -154,9 +164,11 @@ class _Sim1DBuffers:
             ms = cap
         self.struct = Sim1D(n=n, n_samples=ns, max_steps=ms,
                             n_replay=0 if self.replay is None else len(self.replay),
+                            n_rates_replay=0 if self.G0r is None else len(self.G0r),
                             L_max=float(prob.L_max[s]), C0=float(prob.C0[s]),
                             f0=_ptr(self.f0), par=_ptr(self.par), t_samples=_ptr(self.ts),
-                            dt_replay=_ptr(self.replay), f_samples=_ptr(self.f_samples), mom=_ptr(self.mom),
+                            dt_replay=_ptr(self.replay), G0_replay=_ptr(self.G0r), B_replay=_ptr(self.Br),
+                            f_samples=_ptr(self.f_samples), mom=_ptr(self.mom),
                             C=_ptr(self.C), f_final=_ptr(self.f_final), dt_log=_ptr(self.dt_log),
                             G0_log=_ptr(self.G0_log), B_log=_ptr(self.B_log),
                             steps=_ptr(self.steps), status=_ptr(self.status), C_final=_ptr(self.C_final),
@@ -179,10 +191,12 @@ DEFAULT_LOG = 400000
 
 
 def solve1d(prob, s: int = 0, record_f: bool = False, max_steps: int | None = None, dt_replay=None,
-            log_steps: int = DEFAULT_LOG) -> dict:
-    """Run one 1D simulation of `prob` on the CPU; returns samples and final state."""
+            log_steps: int = DEFAULT_LOG, rates_replay=None) -> dict:
+    """Run one 1D simulation of `prob` on the CPU; returns samples and final state.
+
+    rates_replay = (G0[steps], B[steps]): use these rates at the first steps instead of the law."""
     assert prob.ndim == 1
-    buf = _Sim1DBuffers(prob, s, record_f, max_steps, dt_replay, log_steps)
+    buf = _Sim1DBuffers(prob, s, record_f, max_steps, dt_replay, log_steps, rates_replay)
     p = process_of(prob)
     rc = lib().ref_solve1d(C.byref(p), C.byref(buf.struct))
     if rc != 0:
@@ -202,9 +216,11 @@ def solve1d_batch(prob, idx=None, n_threads: int = 0, record_f: bool = False, ma
     return [b.result() for b in bufs], used
 
 
-def tangent1d(prob, s: int = 0, with_f: bool = True, max_steps: int | None = None):
-    """Forward-mode derivatives of the samples w.r.t. (kg, g, kb, b, gamma), schedule frozen.
+def tangent1d(prob, s: int = 0, with_f: bool = True, max_steps: int | None = None, frozen_dt: bool = False):
+    """Forward-mode derivatives of the samples w.r.t. (kg, g, kb, b, gamma).
 
+    frozen_dt=False differentiates the step sizes in the branch each step takes (see
+    pbe_oracle.h); True replays the primal run's step sizes as constants.
     Returns dict with dF [ns, n, 5] (if with_f), dM [ns, 4, 5], dC [ns, 5].
     """
     buf = _Sim1DBuffers(prob, s, False, max_steps, None, 0)
@@ -214,7 +230,8 @@ def tangent1d(prob, s: int = 0, with_f: bool = True, max_steps: int | None = Non
     dM = np.zeros((ns, 4, NTAN))
     dC = np.zeros((ns, NTAN))
     p = process_of(prob)
-    rc = lib().ref_tangent1d(C.byref(p), C.byref(buf.struct), _ptr(dF), _ptr(dM), _ptr(dC))
+    rc = lib().ref_tangent1d(C.byref(p), C.byref(buf.struct), DT_FROZEN if frozen_dt else DT_DIFF, _ptr(dF),
+                             _ptr(dM), _ptr(dC))
     if rc != 0:
         raise RuntimeError(f"ref_tangent1d failed ({rc})")
     out = dict(dM=dM, dC=dC)
@@ -333,7 +350,7 @@ def mlp_vjp(blob, precision: int, z, ybar):
     return g
 
 
-def tangent1d_mlp(prob, s: int, v, with_f: bool = True, max_steps: int | None = None):
+def tangent1d_mlp(prob, s: int, v, with_f: bool = True, max_steps: int | None = None, frozen_dt: bool = False):
     """Closure-law solve: derivatives along the weight direction v (tangent 0) and gamma (tangent 1)."""
     n, ns = int(prob.n_cells[s]), len(prob.t_samples)
     b = _Sim1DBuffers(prob, s, False, max_steps, None, 0)
@@ -343,7 +360,8 @@ def tangent1d_mlp(prob, s: int, v, with_f: bool = True, max_steps: int | None = 
     dM = np.zeros((ns, 4, 2))
     dC = np.zeros((ns, 2))
     p = process_of(prob)
-    rc = lib().ref_tangent1d_mlp(C.byref(p), C.byref(st), _ptr(v), _ptr(dF), _ptr(dM), _ptr(dC))
+    rc = lib().ref_tangent1d_mlp(C.byref(p), C.byref(st), DT_FROZEN if frozen_dt else DT_DIFF, _ptr(v), _ptr(dF),
+                                 _ptr(dM), _ptr(dC))
     assert rc == 0, rc
     return dict(dF=dF, dM=dM, dC=dC)
 

@@ -316,25 +316,28 @@ def estimation(n_sims: int = 1024, n: int = 1000, t_end: float = T_END, n_sample
 
 
 # closure network blob: W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2], then
-# in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
+# in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min lnG0_max
 MLP_H = 64
 MLP_NW = 4546
-MLP_NC = 17
+MLP_NC = 18
+MLP_C_LNG0_MAX = MLP_NW + 17
 MLP_NBLOB = MLP_NW + MLP_NC
 MLP_BF16, MLP_FP64 = 0, 1
 MLP_OFF = dict(W1=0, b1=192, W2=256, b2=4352, W3=4416, b3=4544)
 
 
 def closure_consts(in_shift=(0.1, 30.0, 14.0), in_scale=(10.0, 0.1, 1.0), out_shift=(-4.0, 17.0),
-                   out_scale=(2.0, 2.0), lo=(0.0, -10.0, 6.0), hi=(2.0, 80.0, 22.0), s_min=1e-8) -> np.ndarray:
-    """Normalisation and validity box of the closure inputs (S, T degC, log10 mu_2).
+                   out_scale=(2.0, 2.0), lo=(0.0, -10.0, 6.0), hi=(2.0, 80.0, 22.0), s_min=1e-8,
+                   lnG0_max=-0.7) -> np.ndarray:
+    """Normalisation and validity box of the closure inputs (S, T degC, log10 mu_2), and the
+    largest growth rate the network may return (ln G0 is held at lnG0_max above it).
 
     Defaults fit the closure workload: S up to ~0.3, T in 15..40 degC, mu_2 of
-    the seed ~4e13 um^2/m^3 growing to ~1e15; ln G0 ~ -4 (G0 ~ 0.02 um/s) and
-    ln B ~ 17 (B ~ 2e7 #/(m^3 s)).
+    the seed ~4e13 um^2/m^3 growing to ~1e15; ln G0 ~ -4 (G0 ~ 0.02 um/s, capped
+    at ~0.5 um/s) and ln B ~ 17 (B ~ 2e7 #/(m^3 s)).
     """
     return np.array(list(in_shift) + list(in_scale) + list(out_shift) + list(out_scale) + list(lo) + list(hi)
-                    + [s_min], dtype=np.float32)
+                    + [s_min, lnG0_max], dtype=np.float32)
 
 
 def closure_net(seed_offset: int = 5, out_gain: float = 0.1, consts=None) -> np.ndarray:

@@ -177,3 +177,64 @@ def test_closure_tangent_matches_central_differences(oracle):
         rp, rm = oracle.solve1d(prob.with_(par=pp), s), oracle.solve1d(prob.with_(par=pm), s)
         fd = (rp["mom"] - rm["mom"]) / (2 * hg)
         np.testing.assert_allclose(tan["dM"][..., 1], fd, rtol=1e-5, atol=1e-7 * np.abs(fd).max())
+
+
+def test_growth_rate_clamp_is_a_constant_power_law(oracle):
+    """Output bias above the clamp: ln G0 is held at lnG0_max, so the closure is the constant power
+    law G0 = exp(lnG0_max) (g = 0), and a weight direction that only moves the G0 output has zero
+    derivative while the clamp holds."""
+    blob = W.closure_net()
+    blob[:W.MLP_NW] = 0.0
+    blob[O["b3"]:O["b3"] + 2] = [1.0, -0.3]          # ln G0 = -4 + 2*1 = -2 > lnG0_max
+    blob[W.MLP_C_LNG0_MAX] = -2.8
+    c = blob[W.MLP_NW:].astype(np.float64)
+    assert c[6] + c[8] * 1.0 > c[17]
+    G0 = math.exp(c[17])
+    B = math.exp(c[7] + c[9] * float(np.float32(-0.3)))
+    prob = closure_problem(blob=blob)
+    plain = prob.with_(law=W.LAW_POWER, mlp=None, par=prob.par.copy())
+    plain.par[:, W.P_KG] = G0 / 1e6
+    plain.par[:, W.P_G] = 0.0
+    plain.par[:, W.P_KB] = B
+    plain.par[:, W.P_B] = 0.0
+    v = np.zeros(W.MLP_NW)
+    v[O["b3"]] = 1.0
+    for s in range(prob.n_sims):
+        a, b = oracle.solve1d(prob, s), oracle.solve1d(plain, s)
+        assert a["status"] == b["status"] == 0 and a["steps"] == b["steps"]
+        np.testing.assert_allclose(a["mom"], b["mom"], rtol=1e-12)
+        tan = oracle.tangent1d_mlp(prob, s, v, with_f=False)
+        assert np.all(tan["dM"][..., 0] == 0.0) and np.all(tan["dC"][..., 0] == 0.0)
+
+
+def test_closure_tangent_through_the_cfl_step(oracle):
+    """CFL-limited steps under the closure: derivatives along a weight direction (which moves the
+    network's growth rate, hence the step, the time reached, the ramp temperature and the network's
+    temperature input) agree with central differences of the free-running solve."""
+    consts = W.closure_consts(lnG0_max=3.0)
+    blob = W.closure_net(out_gain=0.5, consts=consts)
+    blob[O["b3"]] = 1.2                       # G0 ~ 0.2 um/s: CFL-limited (dt ~ 6 s) below dt_max = 60 s
+    prob = closure_problem(n_sims=2, n=400, t_end=200.0, blob=blob)
+    prob = prob.with_(dt_max=60.0, par=prob.par.copy(), t_samples=W.uniform_samples(2, 200.0))
+    prob.par[:, W.P_TRAMP] = 500.0
+    h = 2.0 ** -18
+    for s in range(prob.n_sims):
+        r0 = oracle.solve1d(prob, s)
+        assert r0["status"] == 0
+        n_cfl = int(np.sum(r0["dt"] < prob.dt_max * (1 - 1e-12)))
+        assert n_cfl >= 0.9 * r0["steps"], (n_cfl, r0["steps"])
+        v = exact_direction(prob.mlp, 20 + s)
+        tan = oracle.tangent1d_mlp(prob, s, v)
+        frozen = oracle.tangent1d_mlp(prob, s, v, frozen_dt=True)
+        vals = []
+        for sg in (1.0, -1.0):
+            b = prob.mlp.copy()
+            b[:W.MLP_NW] = (b[:W.MLP_NW].astype(np.float64) + sg * h * v).astype(np.float32)
+            r = oracle.solve1d(prob.with_(mlp=b), s)
+            assert r["steps"] == r0["steps"]
+            vals.append(r)
+        for key, tk in (("mom", "dM"), ("C", "dC")):
+            fd = (vals[0][key] - vals[1][key]) / (2 * h)
+            np.testing.assert_allclose(tan[tk][..., 0], fd, rtol=1e-4, atol=1e-6 * np.abs(fd).max())
+            # holding the schedule fixed misses the dependence through the step (5x the tolerance above)
+            assert np.abs(frozen[tk][..., 0] - fd).max() > 5e-4 * np.abs(fd).max()

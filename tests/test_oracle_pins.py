@@ -439,3 +439,185 @@ def test_2d_fvm_converges_to_mom(oracle):
         errs.append(e)
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(orders) >= 0.8, (errs, orders)
+
+
+# --------------------------------------------------------------------------- outflow, CFL bound, split order
+def exact_ssprk3_line(f, G0, gamma, ghost, dt, dL=Fr(1)):
+    """One SSP-RK3 step of the flux form on a line, in Butcher form (c = 0, 1, 1/2; b = 1/6, 1/6, 2/3),
+    exact rationals.  Returns the new line, the number that left through the last face (dt times the
+    b-weighted flux through it) and the three stage fluxes through that face."""
+    n = len(f)
+
+    def fluxes(u):
+        ext = lambda i: ghost if i < 0 else (Fr(0) if i >= n else u[i])
+        out = []
+        for j in range(n + 1):
+            vel = G0 * (1 + Fr(gamma) * j * dL)
+            out.append(vel * (ext(j - 1) + Fr(1, 2) * paper_correction(ext(j - 2), ext(j - 1), ext(j))))
+        return out
+
+    def rhs(F):
+        return [-(F[i + 1] - F[i]) / dL for i in range(n)]
+
+    F1 = fluxes(f)
+    k1 = rhs(F1)
+    F2 = fluxes([f[i] + dt * k1[i] for i in range(n)])
+    k2 = rhs(F2)
+    F3 = fluxes([f[i] + dt * (k1[i] + k2[i]) / 4 for i in range(n)])
+    k3 = rhs(F3)
+    new = [f[i] + dt * (k1[i] + k2[i] + 4 * k3[i]) / 6 for i in range(n)]
+    return new, dt * (F1[n] + F2[n] + 4 * F3[n]) / 6, (F1[n], F2[n], F3[n])
+
+
+def test_outflow_accumulator_and_number_balance_exact(oracle):
+    """Crystals crossing L_max: the oracle's outflow equals dt times the Runge-Kutta-weighted flux
+    through the last face (Butcher weights 1/6, 1/6, 2/3, exact rationals), and the zeroth moment
+    obeys mu0^{n+1} = mu0^n + dt B - (outflow of the step) (SI Eq. (S5) with the flux form of Eq. (8))."""
+    p = tiny_problem(W.SCHEME_SSPRK3, kb=3e8, gamma=0.02)
+    p.f0 = np.array([0.0, 1.0, 3.0, 7.0, 6.0, 2.0, 4.0, 5.0])   # mass at the outer face
+    steps = 2
+    r = oracle.solve1d(p, 0, max_steps=steps)
+    f = [Fr(x) for x in p.f0]
+    out, out_equal, birth = Fr(0), Fr(0), Fr(0)
+    for k in range(steps):
+        G0, B, dt = Fr(r["G0"][k]), Fr(r["B"][k]), Fr(r["dt"][k])
+        f, o, st = exact_ssprk3_line(f, G0, 0.02, B / G0, dt)
+        out += o
+        out_equal += dt * sum(st) / 3
+        birth += dt * B
+    assert out > 0 and r["outflow"] > 0
+    assert abs(Fr(r["outflow"]) - out) <= out * Fr(1, 2 ** 44), (r["outflow"], float(out))
+    # equal stage weights would be a visibly different accumulator at this size
+    assert abs(out_equal - out) > out * Fr(1, 10 ** 4)
+    # number balance of the oracle's own state (dL = 1): nuclei in, outflow out
+    mu0_0 = sum(Fr(x) for x in p.f0)
+    mu0_n = sum(Fr(x) for x in r["f_final"])
+    resid = mu0_n - (mu0_0 + birth - Fr(r["outflow"]))
+    assert abs(resid) <= mu0_n * Fr(1, 2 ** 48), float(resid / mu0_n)
+    assert Fr(r["outflow"]) > mu0_n * Fr(1, 2 ** 30)   # the outflow term is far above the tolerance
+
+
+def test_cfl_step_uses_the_fastest_face(oracle):
+    """SI Eq. (S3) with size-dependent growth: the step is nu*dL over the largest face velocity, found
+    here by brute force over all faces (G0 (1 + gamma L_j), j = 0..n).  With constant rates every step
+    between samples has that length except the one that lands on the sample, and summing
+    dt * max_j G_j / dL over the CFL-limited steps gives nu times their number."""
+    n, L_max, gamma, nu = 100, 1000.0, 2e-3, 0.5
+    p = constant_rate_problem(n=n, L_max=L_max, mean=650.0, sd=40.0, kg=1e-7, g=1.0, gamma=gamma, S=0.5,
+                              t_end=1500.0, n_samples=3, dt_max=1e9, cfl=nu)
+    r = oracle.solve1d(p, 0)
+    G0 = r["G0"][0]
+    assert np.all(r["G0"] == G0)
+    dL = L_max / n
+    faces = np.arange(n + 1) * dL
+    vmax = max(G0 * (1.0 + gamma * x) for x in faces)
+    dt_cfl = nu * dL / vmax
+    # expected schedule: full CFL steps, then the one that lands on the sample time
+    expect, t_prev = [], 0.0
+    for ts in p.t_samples:
+        t = t_prev
+        while True:
+            rem = ts - t
+            if dt_cfl >= rem - 1e-12 * p.t_end:
+                expect.append(("land", rem))
+                break
+            expect.append(("cfl", dt_cfl))
+            t += dt_cfl
+        t_prev = ts
+    assert r["steps"] == len(expect)
+    cfl_idx = [i for i, (k, _) in enumerate(expect) if k == "cfl"]
+    assert len(cfl_idx) > 0.9 * len(expect)
+    np.testing.assert_allclose(r["dt"][cfl_idx], dt_cfl, rtol=1e-15)
+    assert abs(np.sum(r["dt"][cfl_idx] * vmax / dL) - nu * len(cfl_idx)) <= 1e-12 * len(cfl_idx)
+    # stable at the fastest face: no negative density, the number is conserved
+    rr = oracle.solve1d(p, 0, record_f=True)
+    assert rr["f_samples"].min() >= -1e-14 * rr["f_samples"].max()
+    # number: what left through L_max is what the zeroth moment lost
+    np.testing.assert_allclose(rr["mom"][-1, 0] + rr["outflow"], p.f0.sum() * dL, rtol=1e-12)
+
+
+def test_2d_step_is_row_sweep_then_column_sweep_exact(oracle):
+    """One 2D step equals an exact-rational L1 sweep over every row followed by an L2 sweep over every
+    column (Godunov splitting, Sec. 2.1), each an SSP-RK3 step of the 1D flux form, with the corner
+    nucleation split between the two sweeps' inflow faces; the opposite order gives another answer."""
+    n1, n2 = 5, 4
+    T, S = 20.0, 0.25
+    kg1, g1, kg2, g2, kb, b = 3e-7, 1.0, 2e-7, 1.0, 4e8, 2.0
+    par = W._par_row(kg1, g1, kb, b, 0.0, kg2, g2, T0=T, T1=T, t_ramp=1.0)
+    f0 = np.array([[0, 1, 3, 2, 0], [1, 4, 6, 3, 1], [0, 2, 5, 4, 2], [0, 0, 1, 2, 1]], dtype=np.float64)
+    L1m, L2m = 5.0, 4.0
+    p = W.Problem(ndim=2, n_cells=np.array([[n1, n2]], dtype=np.int32), L_max=np.array([[L1m, L2m]]),
+                  f0=f0.ravel(), C0=np.array([W.csat_linear(T) * (1 + S)]), par=par[None, :],
+                  t_samples=np.array([50.0]), t_end=50.0, alpha=0.0, dt_max=1.0, cfl=0.45)
+    r = oracle.solve2d(p, 0, max_steps=1)
+    Sx = p.C0[0] / W.csat_linear(T) - 1.0
+    G1, G2, B = Fr(1e6 * kg1 * Sx ** g1), Fr(1e6 * kg2 * Sx ** g2), Fr(kb * Sx ** b)
+    dt = Fr(r["dt"][0])
+    d1, d2 = Fr(1), Fr(1)
+
+    def sweep_rows(f):
+        out = []
+        for j in range(n2):
+            ghost = B / (2 * d2 * G1) if j == 0 else Fr(0)
+            out.append(exact_ssprk3_line(f[j], G1, 0.0, ghost, dt, d1)[0])
+        return out
+
+    def sweep_cols(f):
+        cols = []
+        for i in range(n1):
+            ghost = B / (2 * d1 * G2) if i == 0 else Fr(0)
+            cols.append(exact_ssprk3_line([f[j][i] for j in range(n2)], G2, 0.0, ghost, dt, d2)[0])
+        return [[cols[i][j] for i in range(n1)] for j in range(n2)]
+
+    f = [[Fr(x) for x in row] for row in f0]
+    want = sweep_cols(sweep_rows(f))
+    other = sweep_rows(sweep_cols(f))
+    got = r["f_final"]
+    scale = max(abs(x) for row in want for x in row)
+    err = max(abs(Fr(got[j, i]) - want[j][i]) for j in range(n2) for i in range(n1))
+    assert err <= scale * Fr(1, 2 ** 44), float(err / scale)
+    diff = max(abs(other[j][i] - want[j][i]) for j in range(n2) for i in range(n1))
+    assert diff > scale * Fr(1, 10 ** 6), float(diff / scale)
+
+
+# --------------------------------------------------------------------------- derivatives through the step size
+def cfl_limited_problem(n=120, t_end=500.0, n_samples=4):
+    """One simulation whose steps are almost all CFL-limited: large dt_max, high supersaturation,
+    size-dependent growth and a cooling ramp (so the time reached matters through T(t))."""
+    p = W.single_sim("mid", n=n, t_end=t_end, n_samples=n_samples)
+    p = p.with_(dt_max=30.0, par=p.par.copy(), C0=p.C0.copy())
+    p.C0[:] = W.csat_linear(40.0) * 1.25
+    p.par[0, W.P_KG] = 6e-7
+    p.par[0, W.P_GAMMA] = 1.2e-3
+    p.par[0, W.P_TRAMP] = 600.0
+    return p
+
+
+def test_tangent_through_the_cfl_step_matches_free_running_differences(oracle):
+    """Derivatives with the step size differentiated in its branch agree with central differences of
+    the free-running solve (same step count), while derivatives with the schedule frozen do not."""
+    p = cfl_limited_problem()
+    base = oracle.solve1d(p, 0, record_f=True)
+    n_cfl = int(np.sum(base["dt"] < p.dt_max * (1 - 1e-12)))
+    assert n_cfl >= 0.9 * base["steps"], (n_cfl, base["steps"])
+    tan = oracle.tangent1d(p, 0)
+    frozen = oracle.tangent1d(p, 0, frozen_dt=True)
+    eps = np.finfo(float).eps
+    worst_frozen = 0.0
+    for d, idx in enumerate([W.P_KG, W.P_G, W.P_KB, W.P_B, W.P_GAMMA]):
+        h = 1e-5 * abs(p.par[0, idx])
+        outs = []
+        for sgn in (+1, -1):
+            q = p.with_(par=p.par.copy())
+            q.par[0, idx] += sgn * h
+            o = oracle.solve1d(q, 0, record_f=True)
+            assert o["steps"] == base["steps"]
+            outs.append(o)
+        for key, tkey in [("mom", "dM"), ("C", "dC"), ("f_samples", "dF")]:
+            want = (outs[0][key] - outs[1][key]) / (2 * h)
+            noise = 1e3 * eps * np.max(np.abs(base[key])) / h
+            tol = 1e-4 * np.max(np.abs(want)) + noise
+            got = tan[tkey][..., d]
+            assert np.max(np.abs(got - want)) <= tol, (d, key, np.max(np.abs(got - want)), tol)
+            worst_frozen = max(worst_frozen, np.max(np.abs(frozen[tkey][..., d] - want)) / tol)
+    assert worst_frozen > 100.0, worst_frozen
