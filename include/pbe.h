@@ -55,7 +55,9 @@ enum { PBE_SIM_OK = 0, PBE_SIM_NONFINITE = 1, PBE_SIM_OUTFLOW = 2, PBE_SIM_FALLB
 /* pbe_problem.flags */
 enum { PBE_FLAG_DEVICE_PTRS = 1,  /* output/cotangent pointers are device memory, stream-ordered */
        PBE_FLAG_RECORD_F = 2,     /* record the number density at every sample time */
-       PBE_FLAG_AUTOTUNE = 4 };   /* pick the launch shape with pbe_tune at create (cached per process) */
+       PBE_FLAG_AUTOTUNE = 4,     /* 2D: pick the launch shape with pbe_tune at create (cached per
+                                     process); 1D: PBE_EUNSUPPORTED (see pbe_tune) */
+       PBE_FLAG_RECORD_RATES = 8 };  /* 1D: record (dt, G0, B) of every step, read with pbe_rate_log */
 
 /* per-sim parameter row */
 enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G2, PBE_P_EG, PBE_P_EB,
@@ -66,17 +68,19 @@ enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G
  * Fig. 5a, in which a network replaces the growth/nucleation rate laws.
  * Blob of PBE_MLP_NW weights then PBE_MLP_NC constants (float):
  *   W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]
- *   in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
+ *   in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min lnG0_max
  * Inputs x = (S, T [degC], log10 mu_2) with S = C/Csat - 1 and mu_2 of the
  * current state; z = (x - in_shift) * in_scale; h1 = tanh(W1 z + b1),
- * h2 = tanh(W2 h1 + b2), y = W3 h2 + b3; ln G0 = out_shift0 + out_scale0 y0
- * (G0 in um/s) and ln B = out_shift1 + out_scale1 y1.  Where S <= s_min,
+ * h2 = tanh(W2 h1 + b2), y = W3 h2 + b3; ln G0 = min(out_shift0 + out_scale0 y0,
+ * lnG0_max) (G0 in um/s; held at the bound, with zero derivative, above it, which
+ * bounds the number of CFL-limited steps) and ln B = out_shift1 + out_scale1 y1.
+ * Where S <= s_min,
  * mu_2 <= 0 or x leaves [lo, hi], the power law with the sim's (kg, g, kb, b)
  * is used and PBE_SIM_FALLBACK is set.  PBE_MLP_BF16: bfloat16 weights and
  * activations on the matrix cores with fp32 accumulation; PBE_MLP_FP64: fp64.
  * The closure runs the SSP-RK3 scheme on grids of up to 1024 cells. */
 #define PBE_MLP_NW 4546
-#define PBE_MLP_NC 17
+#define PBE_MLP_NC 18
 enum { PBE_MLP_BF16 = 0, PBE_MLP_FP64 = 1 };
 
 typedef struct {
@@ -141,15 +145,20 @@ int pbe_solve(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
 int pbe_fetch(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
               int32_t *steps_out, int32_t *status_out);
 
-/* Vector-Jacobian product of the outputs of the last pbe_solve (1D only):
+/* Vector-Jacobian product of the outputs of the last pbe_solve (1D only),
+ * the reverse-mode derivative of the paper's Sec. 4.1 (Eq. (10)) / SI S2.1:
  * given cotangents gf (shape of f_out), gmom (shape of mom_out), gC (shape
  * of C_out) - each may be NULL for zero - write
  *   gpar_out  [S][PBE_NGRAD] = d<cot, outputs>/d(kg, g, kb, b, gamma) per sim,
  *   gmlp_out  law == MLP: [PBE_MLP_NW] d<cot, outputs>/d(closure weights), summed over sims
  *             (may be NULL); ignored for other laws.
- * The step-size schedule of the forward solve is held fixed (it is not
- * differentiated).  Requires ckpt_every > 0 and a completed pbe_solve
- * (PBE_ESTATE otherwise). */
+ * Every step size is differentiated in the branch the forward solve took: a
+ * CFL-limited step (SI Eq. (S3)) through G0 and gamma, a step landing on a
+ * sample time through the time reached, the time through the temperature of
+ * the cooling ramp; steps of dt_max are constants.  Which branch each step
+ * takes, and so the step count, is piecewise constant and not differentiated.
+ * A sim that did not reach t_end (PBE_SIM_NONFINITE or the step cap) gets NaN.
+ * Requires ckpt_every > 0 and a completed pbe_solve (PBE_ESTATE otherwise). */
 int pbe_grad(pbe_handle *h, const double *gf, const double *gmom, const double *gC,
              double *gpar_out, double *gmlp_out);
 
@@ -162,11 +171,22 @@ int pbe_set_mlp(pbe_handle *h, const float *w);
 
 /* The closure network alone (no box, no rates): for raw inputs
  * x[n][3] = (S, T, log10 mu_2) writes y[n][2] (the two network outputs) and
- * dy[n][2][2] = dy_o/d(z0, z2) of the normalised inputs.  x, y, dy are device
+ * dy[n][2][3] = dy_o/dz_i of the normalised inputs.  x, y, dy are device
  * pointers ordered on hip_stream; blob is a host closure blob.  Blocks until
  * done (it copies the blob in and frees its scratch). */
 int pbe_mlp_forward(const float *blob, int32_t precision, int32_t n, const double *x, double *y, double *dy,
                     void *hip_stream);
+
+/* Weight gradient of the closure network alone: gw[PBE_MLP_NW] =
+ * sum_r (dy/dW at z_r)^T ybar_r over n rows of normalised inputs z[n][3] and
+ * output cotangents ybar[n][2] - the contraction pbe_grad performs over the
+ * rows its adjoint sweep leaves (the closure of Sec. 4.2, Fig. 5a, trained
+ * through the solver).  bf16 precision: the same bfloat16 forward and
+ * backward on the matrix cores (fp32 accumulation); fp64: plain FP64.  z,
+ * ybar, gw are device pointers ordered on hip_stream; blob is a host closure
+ * blob.  Blocks until done (it copies the blob in and frees its scratch). */
+int pbe_mlp_vjp(const float *blob, int32_t precision, int32_t n, const double *z, const double *ybar, double *gw,
+                void *hip_stream);
 
 /* One Adam step (Kingma and Ba; the optimiser of Sec. 4.1 / App. C) on device
  * arrays of n floats: w -= lr * mhat / (sqrt(vhat) + eps) with the moment
@@ -178,7 +198,10 @@ int pbe_adam(float *w, float *m, float *v, const double *g, int32_t n, int32_t s
 /* Replace every sim's parameter row (host pointer [S*PBE_NPAR], same checks
  * as pbe_create) without rebuilding the handle, e.g. between optimizer
  * iterations; the handle restarts from the initial condition.  Waits for the
- * handle's queued work first. */
+ * handle's queued work first.  1D with a derived step budget (max_steps = 0 at
+ * create): PBE_ESTATE, nothing changed, if a sim's step bound under the new
+ * kinetics exceeds the budget sized at create (the checkpoints and gradient
+ * rows are sized from it); create the handle with a larger max_steps instead. */
 int pbe_set_par(pbe_handle *h, const double *par);
 
 /* Launch shape chosen by pbe_tune. */
@@ -194,18 +217,17 @@ typedef struct {
 } pbe_tuning;
 
 /* Autotuner: time candidate launch shapes on this handle's own problem and
- * keep the fastest (1D: persistent grid size per kernel class, as a fraction
- * 1/4, 1/2, 1, 2 of what fits the device, one wavefront per simulation; 2D:
- * column-block length 64, 128, 256 or 512 rows).  Wave pairs for grids over
- * 1024 cells are selected with pbe_set_launch.  Each candidate runs the solve from the initial
- * condition, limited to trial_steps steps per simulation (0: to t_end), timed
- * with HIP events.  1D results do not depend on the launch shape; 2D results
- * agree to rounding (the moment partial sums are grouped by column block).
- * The choice is cached per process under the problem's shape (dimension,
- * sizes, closure variant); with use_cache != 0 a cached choice is applied
- * without timing.  Blocks; the handle restarts from the initial condition.
- * out may be NULL.  pbe_create runs this with use_cache = 1 when flags has
- * PBE_FLAG_AUTOTUNE. */
+ * keep the fastest (2D: column-block length 64, 128, 256 or 512 rows).  Each
+ * candidate runs the solve from the initial condition, limited to trial_steps
+ * steps per simulation (0: to t_end), timed with HIP events.  2D results agree
+ * to rounding (the moment partial sums are grouped by column block).  The
+ * choice is cached per process under the problem's shape (dimension, sizes,
+ * closure variant); with use_cache != 0 a cached choice is applied without
+ * timing.  Waits for the handle's queued work first, then blocks; the handle
+ * restarts from the initial condition.  out may be NULL.  pbe_create runs this
+ * with use_cache = 1 when flags has PBE_FLAG_AUTOTUNE.
+ * 1D handles: PBE_EUNSUPPORTED (timing 1D candidates is switched off; apply a
+ * 1D launch shape with pbe_set_launch). */
 int pbe_tune(pbe_handle *h, int32_t trial_steps, int32_t use_cache, pbe_tuning *out);
 
 /* Apply a launch shape without timing (e.g. one pbe_tune chose before): the
@@ -215,6 +237,17 @@ int pbe_tune(pbe_handle *h, int32_t trial_steps, int32_t use_cache, pbe_tuning *
  * restarts from the initial condition.  PBE_EINVAL on a NULL or out-of-range
  * argument. */
 int pbe_set_launch(pbe_handle *h, const pbe_tuning *t);
+
+/* Step sizes and rates the last pbe_solve used (1D, created with
+ * PBE_FLAG_RECORD_RATES): out[s][k][0..2] = (dt, G0 [um/s], B [#/(m^3 s)]) of
+ * step k of sim s (the rates of Sec. 2.1 / App. A, or of the learned closure,
+ * and the step of SI Eq. (S3)) for k < min(steps_s, n_steps), 0 beyond.
+ * n_steps in [1, step budget] (the step budget is max_steps, or the one
+ * derived at create).  out is [S][n_steps][3] doubles, a device pointer
+ * (stream-ordered, returns at once) with PBE_FLAG_DEVICE_PTRS, else host
+ * memory (blocks).  PBE_ESTATE without the flag or before a solve;
+ * PBE_EUNSUPPORTED for 2D handles; PBE_EINVAL for n_steps out of range. */
+int pbe_rate_log(pbe_handle *h, int32_t n_steps, double *out);
 
 /* Release all device memory of the handle.  NULL is a no-op. */
 void pbe_destroy(pbe_handle *h);

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpbe.so")
 
 PBE_OK, PBE_EINVAL, PBE_ENOMEM, PBE_EDEVICE, PBE_ENONFINITE, PBE_ESTATE, PBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-FLAG_DEVICE_PTRS, FLAG_RECORD_F, FLAG_AUTOTUNE = 1, 2, 4
+FLAG_DEVICE_PTRS, FLAG_RECORD_F, FLAG_AUTOTUNE, FLAG_RECORD_RATES = 1, 2, 4, 8
 SIM_OK, SIM_NONFINITE, SIM_OUTFLOW, SIM_FALLBACK, SIM_STEPCAP = 0, 1, 2, 4, 8
 NPAR = 12
 NGRAD = 5
@@ -27,8 +27,8 @@ NGRAD = 5
 # every entry point of include/pbe.h
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
            "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_set_launch", "pbe_destroy", "pbe_strerror",
-           "pbe_last_kernel_ms"]
-MLP_NW, MLP_NC = 4546, 17
+           "pbe_last_kernel_ms", "pbe_rate_log", "pbe_mlp_vjp"]
+MLP_NW, MLP_NC = 4546, 18
 MLP_BF16, MLP_FP64 = 0, 1
 
 _dp = C.POINTER(C.c_double)
@@ -86,6 +86,8 @@ def lib():
         L.pbe_strerror.argtypes = [C.c_int]
         L.pbe_strerror.restype = C.c_char_p
         L.pbe_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.pbe_rate_log.argtypes = [vp, C.c_int32, vp]
+        L.pbe_mlp_vjp.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("pbe_destroy", "pbe_strerror"):
                 getattr(L, name).restype = C.c_int
@@ -102,7 +104,8 @@ def _arr(x, dtype):
     return np.ascontiguousarray(x, dtype=dtype)
 
 
-def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, max_steps=0, autotune=False):
+def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, max_steps=0, autotune=False,
+                        record_rates=False):
     """Build the pbe_problem struct for a workloads.Problem; returns (struct, keepalive)."""
     keep = dict(n_cells=_arr(prob.n_cells.reshape(-1), np.int32), L_max=_arr(prob.L_max.reshape(-1), np.float64),
                 f0=_arr(prob.f0, np.float64), C0=_arr(prob.C0, np.float64), par=_arr(prob.par, np.float64),
@@ -111,7 +114,7 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
     if mlp is not None:
         keep["mlp"] = _arr(mlp, np.float32)
     flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0) | \
-        (FLAG_AUTOTUNE if autotune else 0)
+        (FLAG_AUTOTUNE if autotune else 0) | (FLAG_RECORD_RATES if record_rates else 0)
     st = PbeProblem(ndim=prob.ndim, n_sims=prob.n_sims,
                     n_cells=keep["n_cells"].ctypes.data_as(_ip), L_max=keep["L_max"].ctypes.data_as(_dp),
                     f0=keep["f0"].ctypes.data_as(_dp), C0=keep["C0"].ctypes.data_as(_dp),
@@ -137,7 +140,7 @@ class Solver:
     """
 
     def __init__(self, prob, ckpt_every: int = 0, record_f: bool = False, max_steps: int = 0, stream=None,
-                 autotune: bool = False):
+                 autotune: bool = False, record_rates: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_2411_00742_amd needs a ROCm GPU; none is visible")
@@ -147,7 +150,7 @@ class Solver:
         self.ckpt_every = ckpt_every
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        st, keep = make_problem_struct(prob, ckpt_every, record_f, True, max_steps, autotune)
+        st, keep = make_problem_struct(prob, ckpt_every, record_f, True, max_steps, autotune, record_rates)
         self._h = C.c_void_p()
         _check(lib().pbe_create(C.byref(st), C.c_void_p(self.stream.cuda_stream), C.byref(self._h)), "pbe_create")
         del keep
@@ -225,6 +228,13 @@ class Solver:
         t.pair_long = 1 if pair_long else 0
         _check(lib().pbe_set_launch(self._h, C.byref(t)), "pbe_set_launch")
 
+    def rate_log(self, n_steps: int):
+        """(dt, G0, B) of the first n_steps steps of every sim in the last solve: [S, n_steps, 3]."""
+        t = self.torch
+        o = t.empty((self.S, n_steps, 3), dtype=t.float64, device=self.device)
+        _check(lib().pbe_rate_log(self._h, n_steps, _ptr(o)), "pbe_rate_log")
+        return o
+
     def last_kernel_ms(self):
         a, b = C.c_float(), C.c_float()
         _check(lib().pbe_last_kernel_ms(self._h, C.byref(a), C.byref(b)), "pbe_last_kernel_ms")
@@ -244,7 +254,7 @@ class Solver:
 
 def mlp_forward(blob, precision: int, x):
     """The closure network on raw inputs x[n, 3] = (S, T, log10 mu_2) (device tensor or array):
-    returns device tensors y [n, 2] and dy [n, 2, 2] = dy/d(z0, z2)."""
+    returns device tensors y [n, 2] and dy [n, 2, 3] = dy_o/dz_i."""
     import torch
     b = _arr(blob, np.float32)
     assert b.size == MLP_NW + MLP_NC
@@ -252,11 +262,28 @@ def mlp_forward(blob, precision: int, x):
     xt = torch.as_tensor(x, dtype=torch.float64).to(dev).contiguous().reshape(-1, 3)
     n = xt.shape[0]
     y = torch.empty((n, 2), dtype=torch.float64, device=dev)
-    dy = torch.empty((n, 2, 2), dtype=torch.float64, device=dev)
+    dy = torch.empty((n, 2, 3), dtype=torch.float64, device=dev)
     st = torch.cuda.current_stream()
     _check(lib().pbe_mlp_forward(b.ctypes.data_as(C.POINTER(C.c_float)), precision, n, _ptr(xt), _ptr(y), _ptr(dy),
                                  C.c_void_p(st.cuda_stream)), "pbe_mlp_forward")
     return y, dy
+
+
+def mlp_vjp(blob, precision: int, z, ybar):
+    """Weight gradient sum_r (dy/dW at z_r)^T ybar_r of the closure network over rows of
+    normalised inputs z[n, 3] and output cotangents ybar[n, 2]: a [MLP_NW] device tensor."""
+    import torch
+    b = _arr(blob, np.float32)
+    assert b.size == MLP_NW + MLP_NC
+    dev = torch.device("cuda", torch.cuda.current_device())
+    zt = torch.as_tensor(z, dtype=torch.float64).to(dev).contiguous().reshape(-1, 3)
+    yt = torch.as_tensor(ybar, dtype=torch.float64).to(dev).contiguous().reshape(-1, 2)
+    assert zt.shape[0] == yt.shape[0]
+    gw = torch.empty(MLP_NW, dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream()
+    _check(lib().pbe_mlp_vjp(b.ctypes.data_as(C.POINTER(C.c_float)), precision, zt.shape[0], _ptr(zt), _ptr(yt),
+                             _ptr(gw), C.c_void_p(st.cuda_stream)), "pbe_mlp_vjp")
+    return gw
 
 
 class Adam:
@@ -286,8 +313,9 @@ def _autograd_function():
         """Differentiable batched solve: kinetics (kg, g, kb, b, gamma) per sim -> recorded outputs.
 
         forward(par5 [S, 5] float64, solver) -> (f, mom, C); backward runs the
-        library's discrete adjoint (pbe_grad) with the solve's step schedule held
-        fixed.  The solver must have been created with ckpt_every > 0.
+        library's discrete adjoint (pbe_grad), which differentiates every step size
+        in the branch the solve took.  The solver must have been created with
+        ckpt_every > 0.
         """
 
         @staticmethod

@@ -1,10 +1,16 @@
 // Discrete adjoint of the batched 1D solve (gfx950, FP64).
 //
 // Reverse-mode derivative of the recorded outputs (samples of f, mu_0..mu_3
-// and C) with respect to each simulation's (kg, g, kb, b, gamma), with the
-// forward step-size schedule held fixed.  The paper obtains such gradients
-// by reverse-mode AD with checkpointing (Sec. 4.1, SI S2.1); here the adjoint
-// of the time loop is written by hand.
+// and C) with respect to each simulation's (kg, g, kb, b, gamma).  The paper
+// obtains such gradients by reverse-mode AD with checkpointing through the
+// whole time loop (Sec. 4.1, SI S2.1); here the adjoint of the time loop is
+// written by hand.  The step size is differentiated in the branch each step
+// takes: a CFL-limited step nu dL / (G0 (1 + gamma L_max)) (SI Eq. (S3))
+// depends on the growth rate and gamma, a step that lands on a sample time
+// depends on the time reached, and the time reached moves the temperature of
+// the cooling ramp, hence the solubility and the rates; a step of dt_max is a
+// constant.  The schedule itself (which branch, how many steps) is piecewise
+// constant in the parameters and has no derivative.
 //
 // One wavefront per simulation, same register layout as the forward kernel.
 // For each checkpoint segment (ckpt_every steps), last to first:
@@ -156,8 +162,10 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     for (int k = 0; k < K; ++k) lam[k] = 0.0;
     if (A.gf && A.gf_is_final) load_cells(lam, A.gf + base, i0, g.npad, 0.0);
     double lamC = 0.0;
+    double lamT = 0.0;   // adjoint of the time reached after the step being reversed
     double gk[4] = {0.0, 0.0, 0.0, 0.0};
-    double gam = 0.0;
+    double gam = 0.0;    // per lane: gamma through the face weights
+    double gams = 0.0;   // wave-uniform: gamma through the CFL step
     int qs = ns - 1;   // next sample (from the end) whose cotangent is still to be added
     // step index of sample qs, and the bracket of sample times around the
     // reverse walk's current time (nx samples lie at or before it; t_lo is the
@@ -207,11 +215,15 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 r.B = cr.B;
                 if (lane == 0) {
                     double* tr = tapeR + (int64_t)(m - m0) * kClosureTape;
-                    tr[0] = cr.fallback ? 1.0 : 0.0;
+                    tr[0] = (cr.fallback ? 1.0 : 0.0) + (cr.clamped ? 2.0 : 0.0);
                     tr[1] = cr.G0; tr[2] = cr.B;
                     tr[3] = cr.z[0]; tr[4] = cr.z[1]; tr[5] = cr.z[2];
-                    tr[6] = cr.dy[0][0]; tr[7] = cr.dy[1][0]; tr[8] = cr.dy[0][1]; tr[9] = cr.dy[1][1];
-                    tr[10] = mu2;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        tr[6 + 2 * i] = cr.dy[0][i];
+                        tr[7 + 2 * i] = cr.dy[1][i];
+                    }
+                    tr[12] = mu2;
                 }
             }
             double dt;
@@ -281,13 +293,16 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 t_lo = nx > 0 ? uniform(ts[nx - 1]) : -__builtin_huge_val();
             }
             Rates r;
-            bool fb = true;   // plain power law at this step
-            double cz[3] = {0.0, 0.0, 0.0}, cj[4] = {0.0, 0.0, 0.0, 0.0}, cmu2 = 0.0;
+            bool fb = true;        // plain power law at this step
+            bool clamped = false;  // closure: ln G0 held at its bound (no derivative through G0)
+            double cz[3] = {0.0, 0.0, 0.0}, cj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, cmu2 = 0.0;
             if constexpr (CL == kClosureNone) {
                 r = rates_plain(p, q, Cm, tm);
             } else {
                 const double* tr = tapeR + (int64_t)(m - 1 - m0) * kClosureTape;
-                fb = uniform(tr[0]) != 0.0;
+                const int flags = (int)uniform(tr[0]);
+                fb = (flags & 1) != 0;
+                clamped = (flags & 2) != 0;
                 if (fb) {
                     const Process pp{PBE_LAW_POWER, p.scheme, p.sol_law, p.cs0, p.cs1, p.alpha, p.cfl, p.dt_max,
                                      p.t_end};
@@ -299,12 +314,12 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
 #pragma unroll
                     for (int i = 0; i < 3; ++i) cz[i] = uniform(tr[3 + i]);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) cj[i] = uniform(tr[6 + i]);
-                    cmu2 = uniform(tr[10]);
+                    for (int i = 0; i < 6; ++i) cj[i] = uniform(tr[6 + i]);
+                    cmu2 = uniform(tr[12]);
                 }
             }
             double dt;
-            (void)choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_hi, &dt);
+            const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_hi, &dt);
             const double ghost = inflow_ghost(r.B, r.G0);
             const double c = courant(dt, r.G0, inv_dL);
 
@@ -363,24 +378,44 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     lam[k] = padk ? 0.0 : fma(p.alpha * lamC, L * L * L * dL, l);
                 }
             }
-            // rates: c = dt G0/dL, ghost = B/G0
+            // rates and step: c = dt G0/dL, ghost = B/G0; t^m = t^{m-1} + dt, or
+            // the sample time the step lands on (a constant)
             const double cb = wave_sum(cbar);
             const double gb = wave_sum(gbar);
-            double G0b = cb * dt / dL, Bb = 0.0;
+            double dtb = (hit ? 0.0 : lamT) + cb * r.G0 * inv_dL;   // adjoint of dt
+            double lamT_prev = hit ? 0.0 : lamT;                    // adjoint of t^{m-1}
+            double G0b = cb * dt * inv_dL, Bb = 0.0;
             if (r.G0 > 0.0) {
                 Bb = gb / r.G0;
                 G0b -= gb * ghost / r.G0;
             }
+            if (hit) {
+                lamT_prev -= dtb;   // dt = t_next - t^{m-1}
+            } else if (dt < p.dt_max) {
+                // CFL-limited: dt = nu dL / (G0 (1 + gamma L_max))
+                const double wmax = fma(q.gamma, Lmax, 1.0);
+                G0b -= dtb * dt / r.G0;
+                gams -= dtb * dt * Lmax / wmax;
+            }
+            // temperature of the ramp at t^{m-1}, the solubility and its slope
+            const double Tm = temperature(q, tm);
+            const double Csat = solubility(p, Tm);
+            const double dCsat = p.sol_law == PBE_SOL_EXP ? p.cs1 * Csat : p.cs1;
+            const double dTdt = (q.tr > 0.0 && tm < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0;
+            // dS/dT = -(C/Csat) Csat'(T) / Csat
+            const double dSdT = -(Cm / Csat) * dCsat / Csat;
+            double Tb = 0.0;
             if (!fb) {
-                // closure: ln G0 = a0 + s0 y0, ln B = a1 + s1 y1 with y = net(z),
-                // z0 = (S - h0) k0, z2 = (log10 mu2 - h2) k2
+                // closure: ln G0 = a0 + s0 y0 (held at its bound when clamped),
+                // ln B = a1 + s1 y1 with y = net(z), z0 = (S - h0) k0,
+                // z1 = (T - h1) k1, z2 = (log10 mu2 - h2) k2
                 const double* kc = a.cd.c;
-                const double yb0 = G0b * r.G0 * uniform(kc[kCOutScale]);
+                const double yb0 = clamped ? 0.0 : G0b * r.G0 * uniform(kc[kCOutScale]);
                 const double yb1 = Bb * r.B * uniform(kc[kCOutScale + 1]);
-                const double Csat = solubility(p, temperature(q, tm));
                 const double Sbar = (yb0 * cj[0] + yb1 * cj[1]) * uniform(kc[kCInScale]);
                 lamC += Sbar / Csat;
-                const double mbar = (yb0 * cj[2] + yb1 * cj[3]) * uniform(kc[kCInScale + 2]) / (cmu2 * 2.302585092994046);
+                Tb = (yb0 * cj[2] + yb1 * cj[3]) * uniform(kc[kCInScale + 1]) + Sbar * dSdT;
+                const double mbar = (yb0 * cj[4] + yb1 * cj[5]) * uniform(kc[kCInScale + 2]) / (cmu2 * 2.302585092994046);
                 LaneGeom g6 = g;
                 asm volatile("" : "+v"(g6.xb));
 #pragma unroll
@@ -394,10 +429,16 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     rw[0] = cz[0]; rw[1] = cz[1]; rw[2] = cz[2]; rw[3] = yb0; rw[4] = yb1;
                 }
             } else if (r.S > 0.0) {
-                const double Csat = solubility(p, temperature(q, tm));
                 const double dGdS = q.g * r.G0 / r.S;
                 const double dBdS = q.b * r.B / r.S;
-                lamC += (G0b * dGdS + Bb * dBdS) / Csat;
+                const double Sbar = G0b * dGdS + Bb * dBdS;
+                lamC += Sbar / Csat;
+                Tb = Sbar * dSdT;
+                if (CL == kClosureNone && p.law == PBE_LAW_ARRHENIUS) {
+                    // exp(-E/(T + 273.15)) factors
+                    const double iT = 1.0 / (Tm + 273.15);
+                    Tb += (G0b * r.G0 * q.Eg + Bb * r.B * q.Eb) * (iT * iT);
+                }
                 gk[0] += G0b * 1e6 * r.Sg * r.arrG;
                 gk[1] += G0b * r.G0 * r.lnS;
                 gk[2] += Bb * r.Sb * r.arrB;
@@ -407,10 +448,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 double* rw = rows + (int64_t)(m - 1) * 5;
                 rw[0] = 0.0; rw[1] = 0.0; rw[2] = 0.0; rw[3] = 0.0; rw[4] = 0.0;
             }
+            lamT = uniform(fma(Tb, dTdt, lamT_prev));
             lamC = uniform(lamC);
         }
     }
-    const double gg = wave_sum(gam);
+    const double gg = wave_sum(gam) + gams;
     if (lane == 0) {
         double* o = A.gpar + (int64_t)s * PBE_NGRAD;
         o[0] = gk[0]; o[1] = gk[1]; o[2] = gk[2]; o[3] = gk[3]; o[4] = gg;

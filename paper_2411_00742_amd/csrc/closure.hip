@@ -12,6 +12,7 @@
 // index as the contraction dimension.  Per-wave partial gradients are summed
 // in a fixed order by a second kernel, so the result does not depend on
 // scheduling.
+#include <algorithm>
 #include <cmath>
 
 #include "closure_device.h"
@@ -83,14 +84,14 @@ __global__ void k_pack_closure(const float* __restrict__ blob, PackOut o) {
     for (int i = tid; i < kMlpNC; i += nth) o.c[i] = (double)blob[kMlpNW + i];
 }
 
-// Standalone forward on raw inputs x[n][3] (no box): y[n][2], dy[n][2][2] = dy/d(z0, z2).
+// Standalone forward on raw inputs x[n][3] (no box): y[n][2], dy[n][2][3] = dy_o/dz_i.
 __global__ __launch_bounds__(64) void k_closure_forward(ClosureDev cd, int n, const double* __restrict__ x,
                                                          double* __restrict__ y, double* __restrict__ dy) {
     for (int r = blockIdx.x; r < n; r += gridDim.x) {
         double z[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) z[i] = uniform((uniform(x[3 * r + i]) - cd.c[kCInShift + i]) * cd.c[kCInScale + i]);
-        double yy[2], dd[2][2];
+        double yy[2], dd[2][3];
         if (cd.precision == PBE_MLP_FP64)
             net_fp64<true>(cd, z[0], z[1], z[2], yy, dd);
         else
@@ -98,11 +99,26 @@ __global__ __launch_bounds__(64) void k_closure_forward(ClosureDev cd, int n, co
         if (threadIdx.x == 0) {
             y[2 * r] = yy[0];
             y[2 * r + 1] = yy[1];
-            dy[4 * r + 0] = dd[0][0];
-            dy[4 * r + 1] = dd[0][1];
-            dy[4 * r + 2] = dd[1][0];
-            dy[4 * r + 3] = dd[1][1];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                dy[6 * r + i] = dd[0][i];
+                dy[6 * r + 3 + i] = dd[1][i];
+            }
         }
+    }
+}
+
+// rows[r] = (z0, z1, z2, ybar0, ybar1) for r < n, zero rows up to row_cap
+__global__ void k_stage_rows(int n, int row_cap, const double* __restrict__ z, const double* __restrict__ ybar,
+                             double* __restrict__ rows) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < row_cap; r += gridDim.x * blockDim.x) {
+        double* q = rows + (size_t)r * 5;
+        const bool in = r < n;
+        q[0] = in ? z[3 * r] : 0.0;
+        q[1] = in ? z[3 * r + 1] : 0.0;
+        q[2] = in ? z[3 * r + 2] : 0.0;
+        q[3] = in ? ybar[2 * r] : 0.0;
+        q[4] = in ? ybar[2 * r + 1] : 0.0;
     }
 }
 
@@ -424,6 +440,12 @@ hipError_t launch_closure_grad(const ClosureDev& cd, const double* rows, const i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_partials, dim3((kMlpNW + 255) / 256), dim3(256), 0, st, partial, n_blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_rows(int n, int row_cap, const double* z, const double* ybar, double* rows, hipStream_t st) {
+    const int blocks = std::max(1, std::min(1024, (row_cap + 255) / 256));
+    hipLaunchKernelGGL(k_stage_rows, dim3(blocks), dim3(256), 0, st, n, row_cap, z, ybar, rows);
     return hipGetLastError();
 }
 

@@ -8,8 +8,8 @@
 //   fp64  plain FP64 vector arithmetic, one hidden unit per lane.
 // The bf16 path is written in transposed form, out^T = W * in^T: the weights
 // are the A operand (16 output units per tile) and the network inputs are the
-// B operand's columns.  Column 0 carries the network input; columns 1 and 2
-// optionally carry the forward tangents d/dz0 and d/dz2 used by the adjoint;
+// B operand's columns.  Column 0 carries the network input; columns 1, 2 and 3
+// optionally carry the forward tangents d/dz0, d/dz1 and d/dz2 used by the adjoint;
 // in the batched backward kernel all 16 columns are different inputs.  The
 // host packs every A operand so that the k index of a lane's elements matches
 // where the previous layer's accumulator left the same unit in that lane, so
@@ -27,11 +27,12 @@ namespace pbe {
 
 constexpr int kMlpH = 64;
 constexpr int kMlpNW = 4546;     // weights in the blob
-constexpr int kMlpNC = 17;       // constants after the weights
+constexpr int kMlpNC = 18;       // constants after the weights
 // blob offsets: W1[64][3] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]
 constexpr int kOffW1 = 0, kOffB1 = 192, kOffW2 = 256, kOffB2 = 4352, kOffW3 = 4416, kOffB3 = 4544;
-// constants: in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min
-enum { kCInShift = 0, kCInScale = 3, kCOutShift = 6, kCOutScale = 8, kCLo = 10, kCHi = 13, kCSmin = 16 };
+// constants: in_shift[3] in_scale[3] out_shift[2] out_scale[2] lo[3] hi[3] s_min lnG0_max
+enum { kCInShift = 0, kCInScale = 3, kCOutShift = 6, kCOutScale = 8, kCLo = 10, kCHi = 13, kCSmin = 16,
+       kCLnG0Max = 17 };
 
 namespace dev {
 
@@ -88,7 +89,7 @@ __device__ __forceinline__ float from_column0(float v) {
 }
 
 // Hidden activation of one accumulator tile.  Column 0: t = tanh(pre);
-// tangent columns 1..2 (TAN): pre * (1 - t0^2) with t0 the column-0 value of
+// tangent columns 1..3 (TAN): pre * (1 - t0^2) with t0 the column-0 value of
 // the same unit; other columns stay 0 (their pre-activation is 0).
 template <bool TAN>
 __device__ __forceinline__ void activate(f32x4 d, float (&h)[4], float (&t)[4]) {
@@ -114,20 +115,20 @@ __device__ __forceinline__ f32x4 bias_tile(const float* b, int t, bool use) {
     return r;
 }
 
-// bf16 network on one input (column 0).  With TAN, columns 1 and 2 carry
-// d/dz0 and d/dz2 and dy[o][0], dy[o][1] return dy_o/dz0 and dy_o/dz2.
+// bf16 network on one input (column 0).  With TAN, column 1 + i carries
+// d/dz_i and dy[o][i] returns dy_o/dz_i (i = 0, 1, 2).
 // All lanes must be active.  Results are wave-uniform.
 template <bool TAN>
 __device__ __forceinline__ void net_bf16(const ClosureDev& cd, double z0, double z1, double z2, double (&y)[2],
-                                         double (&dy)[2][2]) {
+                                         double (&dy)[2][3]) {
     const int lane = threadIdx.x & 63;
     const int c = lane & 15, g = lane >> 4;
     // layer-1 B operand (16 deep: element e of lane group g is input k = 4g + e)
     s16x4 b1 = {0, 0, 0, 0};
     const bool col0 = (c == 0) && (g == 0);
     b1.x = col0 ? (short)bf16_bits((float)z0) : (TAN && c == 1 && g == 0 ? (short)0x3F80 : (short)0);
-    b1.y = col0 ? (short)bf16_bits((float)z1) : (short)0;
-    b1.z = col0 ? (short)bf16_bits((float)z2) : (TAN && c == 2 && g == 0 ? (short)0x3F80 : (short)0);
+    b1.y = col0 ? (short)bf16_bits((float)z1) : (TAN && c == 2 && g == 0 ? (short)0x3F80 : (short)0);
+    b1.z = col0 ? (short)bf16_bits((float)z2) : (TAN && c == 3 && g == 0 ? (short)0x3F80 : (short)0);
     float h[4][4], tt[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -154,10 +155,11 @@ __device__ __forceinline__ void net_bf16(const ClosureDev& cd, double z0, double
     y[0] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[0]), 0));
     y[1] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[1]), 0));
     if (TAN) {
-        dy[0][0] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[0]), 1));
-        dy[1][0] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[1]), 1));
-        dy[0][1] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[0]), 2));
-        dy[1][1] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[1]), 2));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            dy[0][i] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[0]), 1 + i));
+            dy[1][i] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(o[1]), 1 + i));
+        }
     }
 }
 
@@ -170,7 +172,7 @@ __device__ __forceinline__ double bcast(double v, int src) {
 // fp64 network on one input, hidden unit j in lane j.  Same outputs as net_bf16.
 template <bool TAN>
 __device__ __forceinline__ void net_fp64(const ClosureDev& cd, double z0, double z1, double z2, double (&y)[2],
-                                         double (&dy)[2][2]) {
+                                         double (&dy)[2][3]) {
 #pragma clang fp contract(off)
     const int j = threadIdx.x & 63;
     const double* w = cd.w64;
@@ -181,13 +183,14 @@ __device__ __forceinline__ void net_fp64(const ClosureDev& cd, double z0, double
     a1 = a1 + w12 * z2;
     const double h1 = tanh64(a1);
     const double s1 = 1.0 - h1 * h1;
-    const double t10 = w10 * s1, t12 = w12 * s1;
-    double a2 = w[kOffB2 + j], u0 = 0.0, u2 = 0.0;
+    const double t10 = w10 * s1, t11 = w11 * s1, t12 = w12 * s1;
+    double a2 = w[kOffB2 + j], u0 = 0.0, u1 = 0.0, u2 = 0.0;
     for (int i = 0; i < kMlpH; ++i) {
         const double wij = w[kOffW2 + i * kMlpH + j];
         a2 = a2 + wij * bcast(h1, i);
         if (TAN) {
             u0 = u0 + wij * bcast(t10, i);
+            u1 = u1 + wij * bcast(t11, i);
             u2 = u2 + wij * bcast(t12, i);
         }
     }
@@ -199,20 +202,23 @@ __device__ __forceinline__ void net_fp64(const ClosureDev& cd, double z0, double
         y[o] = w[kOffB3 + o] + wave_sum(w3 * h2);
         if (TAN) {
             dy[o][0] = wave_sum(w3 * (u0 * s2));
-            dy[o][1] = wave_sum(w3 * (u2 * s2));
+            dy[o][1] = wave_sum(w3 * (u1 * s2));
+            dy[o][2] = wave_sum(w3 * (u2 * s2));
         }
     }
 }
 
 // Closure rates for one simulation step.  S = C/Csat - 1 (unclipped),
 // x = (S, T, log10 mu2).  Inside the box the network gives G0 [um/s] and B;
-// outside it the plain power law stands in (fallback).  With TAN also returns
-// the normalised inputs and dy/dz0, dy/dz2 for the adjoint.
+// outside it the plain power law stands in (fallback).  The network's log
+// growth rate is trusted up to lnG0_max and held there above it (clamped:
+// no derivative through G0), which bounds the steps a CFL-limited solve
+// takes.  With TAN also returns the normalised inputs and dy/dz for the adjoint.
 struct ClosureRates {
     double G0, B, S;
-    bool fallback;
+    bool fallback, clamped;
     double z[3];
-    double dy[2][2];
+    double dy[2][3];
 };
 
 template <bool TAN, int PREC>
@@ -229,7 +235,9 @@ __device__ __forceinline__ ClosureRates closure_rates(const ClosureDev& cd, cons
 #pragma unroll
     for (int i = 0; i < 3; ++i) inside = inside && x[i] >= uniform(k[kCLo + i]) && x[i] <= uniform(k[kCHi + i]);
     r.fallback = uniform((int)!inside) != 0;
-    r.dy[0][0] = r.dy[0][1] = r.dy[1][0] = r.dy[1][1] = 0.0;
+    r.clamped = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r.dy[0][i] = r.dy[1][i] = 0.0;
     if (r.fallback) {
         r.z[0] = r.z[1] = r.z[2] = 0.0;
         const Process pp{PBE_LAW_POWER, p.scheme, p.sol_law, p.cs0, p.cs1, p.alpha, p.cfl, p.dt_max, p.t_end};
@@ -245,11 +253,17 @@ __device__ __forceinline__ ClosureRates closure_rates(const ClosureDev& cd, cons
         net_fp64<TAN>(cd, r.z[0], r.z[1], r.z[2], y, r.dy);
     else
         net_bf16<TAN>(cd, r.z[0], r.z[1], r.z[2], y, r.dy);
-    r.G0 = uniform(exp64(uniform(k[kCOutShift]) + uniform(k[kCOutScale]) * uniform(y[0])));
+    const double lnG = uniform(uniform(k[kCOutShift]) + uniform(k[kCOutScale]) * uniform(y[0]));
+    const double lnG_max = uniform(k[kCLnG0Max]);
+    r.clamped = lnG > lnG_max;
+    r.G0 = uniform(exp64(r.clamped ? lnG_max : lnG));
     r.B = uniform(exp64(uniform(k[kCOutShift + 1]) + uniform(k[kCOutScale + 1]) * uniform(y[1])));
     if (TAN) {
-        r.dy[0][0] = uniform(r.dy[0][0]); r.dy[0][1] = uniform(r.dy[0][1]);
-        r.dy[1][0] = uniform(r.dy[1][0]); r.dy[1][1] = uniform(r.dy[1][1]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            r.dy[0][i] = uniform(r.dy[0][i]);
+            r.dy[1][i] = uniform(r.dy[1][i]);
+        }
     }
     return r;
 }

@@ -89,6 +89,10 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         }
         // nucleation: ghost cells at L < 0 hold B/G0 so the flux through L = 0 is B
         const double ghost = inflow_ghost(r.B, r.G0);
+        if (a.rate_log && lane == 0) {   // opt-in record of the step size and rates (step < step_cap here)
+            double* rl = a.rate_log + ((int64_t)s * a.step_cap + step) * 3;
+            rl[0] = dt; rl[1] = r.G0; rl[2] = r.B;
+        }
 
         if (step == ck_at) {
             const int c = ck_c++;

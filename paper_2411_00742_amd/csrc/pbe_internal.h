@@ -25,7 +25,7 @@ struct ClosureDev {
     const uint4* a2t;        // W2 transposed, for the backward [4][2][64]
     const float* bias;       // b1[64] b2[64] b3[2] pad[2]
     const float* w3r;        // W3 rounded to bfloat16, as float [2][64]
-    const double* c;         // the 17 constants (normalisation, output scaling, box, s_min)
+    const double* c;         // the 18 constants (normalisation, output scaling, box, s_min, lnG0_max)
     int32_t precision;       // PBE_MLP_BF16 or PBE_MLP_FP64
     int32_t pad_;
 };
@@ -72,6 +72,7 @@ struct Fvm1dArgs {
     int32_t pair_long;         // 1: class 2 runs grids > 1024 cells on wave pairs
     int32_t closure;           // kClosure*: which rate law the kernels run
     ClosureDev cd;             // closure == kClosureBf16 / kClosureFp64
+    double* rate_log;          // [S][step_cap][3] (dt, G0, B) of every step, or null
 };
 
 // Adjoint of the 1D solve (reverse sweep over checkpointed segments).
@@ -89,8 +90,9 @@ struct Adj1dArgs {
     int32_t row_cap;           // rows per simulation (>= step_cap, multiple of 16)
     int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
 };
-// per taped step: fallback flag, G0, B, z0, z1, z2, dy0/dz0, dy1/dz0, dy0/dz2, dy1/dz2, mu2
-constexpr int kClosureTape = 11;
+// per taped step: flags (1 = fallback, 2 = ln G0 clamped), G0, B, z0, z1, z2,
+// dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2
+constexpr int kClosureTape = 13;
 
 // 2D Godunov-split solver: per global step an L1 row sweep (in place), an L2
 // column march (double buffered) with moment partials, and a per-sim finalize.
@@ -172,12 +174,13 @@ hipError_t launch_cols2d(const Fvm2dArgs& a, int parity, hipStream_t st);
 hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st);
 hipError_t launch_out2d(const Fvm2dArgs& a, double* f_out, hipStream_t st);
 // learned closure (closure.hip)
-constexpr int kMlpWeights = 4546, kMlpConsts = 17;
+constexpr int kMlpWeights = 4546, kMlpConsts = 18;
 size_t closure_pack_bytes();
 hipError_t pack_closure(const float* d_blob, void* mem, int precision, ClosureDev* cd, hipStream_t st);
 hipError_t launch_closure_forward(const ClosureDev& cd, int n, const double* x, double* y, double* dy, hipStream_t st);
 hipError_t launch_closure_grad(const ClosureDev& cd, const double* rows, const int32_t* steps, int n_sims,
                                int row_cap, double* partial, int n_blocks, double* out, hipStream_t st);
+hipError_t launch_stage_rows(int n, int row_cap, const double* z, const double* ybar, double* rows, hipStream_t st);
 hipError_t launch_adam(float* w, float* m, float* v, const double* g, int n, int step, float lr, float b1, float b2,
                        float eps, hipStream_t st);
 

@@ -399,3 +399,37 @@ def random_tiny(seed: int, n: int, t_end: float = 50.0, n_samples: int = 5, gamm
     return Problem(ndim=1, n_cells=np.array([n], dtype=np.int32), L_max=np.array([1000.0]), f0=f0,
                    C0=np.array([C0]), par=_par_row(kg, g, kb, b, gm)[None, :],
                    t_samples=uniform_samples(n_samples, t_end), t_end=t_end, name=f"tiny-{seed}-N{n}")
+
+
+def cfl_limited(n_sims: int = 24, n_lo: int = 4, n_hi: int = 2048, t_end: float = 600.0, n_samples: int = 5,
+                seed_offset: int = 6, dt_max: float = 60.0, sizes=None) -> Problem:
+    """Simulations whose steps are set by the CFL bound rather than by dt_max.
+
+    High initial supersaturation (C0 = Csat(40)*(1 + U[0.15, 0.3])), fast growth
+    (kg ~ log-U[3e-7, 1e-6] m/s), size-dependent growth gamma ~ U[0, 2e-3] 1/um, a
+    large step cap dt_max and a cooling ramp of U[0.3, 1.0]*t_end, so that the
+    step size, and with it the time reached and the temperature, depend on the
+    rates.  Sample times are irregular (uniform draws, sorted, the last at t_end)
+    so they are not multiples of any step.  Grid sizes N ~ U{n_lo..n_hi} unless
+    `sizes` is given.
+    """
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    ns_, pars, seeds, C0 = [], [], [], []
+    for i in range(n_sims):
+        kg = rng.log_uniform(3e-7, 1e-6)
+        g = rng.uniform_range(1.0, 2.0)
+        kb = rng.log_uniform(1e8, 1e10)
+        b = rng.uniform_range(1.0, 3.0)
+        gamma = rng.uniform_range(0.0, 2e-3)
+        n = rng.randint(n_lo, n_hi) if sizes is None else int(sizes[i])
+        c_rel = rng.uniform_range(0.15, 0.3)
+        t_ramp = rng.uniform_range(0.3, 1.0) * t_end
+        ns_.append(n)
+        pars.append(_par_row(kg, g, kb, b, gamma, t_ramp=t_ramp))
+        seeds.append(gaussian_seed_1d(n, 1000.0, 200.0, 30.0, 1e9))
+        C0.append(csat_linear(T_HOT) * (1.0 + c_rel))
+    ts = sorted(rng.uniform_range(0.05, 0.95) * t_end for _ in range(n_samples - 1)) + [t_end]
+    return Problem(ndim=1, n_cells=np.array(ns_, dtype=np.int32), L_max=np.full(n_sims, 1000.0),
+                   f0=np.concatenate(seeds), C0=np.array(C0), par=np.array(pars),
+                   t_samples=np.array(ts, dtype=np.float64), t_end=t_end, dt_max=dt_max,
+                   name=f"cfl-limited-{n_sims}x[{n_lo},{n_hi}]")

@@ -15,9 +15,10 @@ def outputs(s):
     return {k: v.cpu().numpy() for k, v in s.solve().items()}
 
 
-@pytest.mark.skip(reason="the 1D autotuner with graph-captured trials and wave-pair candidates crashed the host "
-                         "process inside the HIP runtime (SIGSEGV in pbe_tune, no GPU fault); that path is switched "
-                         "off and this case stays off the GPU until the cause is shown")
+@pytest.mark.skip(reason="an earlier form of the 1D autotuner (graph-captured trials with wave-pair candidates) "
+                         "crashed the host process inside the HIP runtime (SIGSEGV in pbe_tune, no GPU fault); the "
+                         "cause has not been shown, so 1D tuning returns PBE_EUNSUPPORTED and this case stays off "
+                         "the GPU")
 def test_tuned_1d_launch_gives_identical_results(torch_cuda):
     import paper_2411_00742_amd as pbe
     prob = W.batched(n_sims=300, n_lo=64, n_hi=2048, t_end=300.0, n_samples=3)
@@ -35,6 +36,24 @@ def test_tuned_1d_launch_gives_identical_results(torch_cuda):
     c = outputs(s2)
     s2.close()
     same_partition_as_default(a, c, t["pair_long"])
+
+
+def test_1d_tuning_is_switched_off(torch_cuda):
+    """pbe_tune and PBE_FLAG_AUTOTUNE refuse 1D handles (before any device work)."""
+    import paper_2411_00742_amd as pbe
+    prob = W.batched(n_sims=4, n_lo=64, n_hi=300, t_end=60.0, n_samples=2)
+    s = pbe.Solver(prob)
+    with pytest.raises(pbe.PBEError) as e:
+        s.tune()
+    assert e.value.code == pbe.PBE_EUNSUPPORTED
+    a = outputs(s)                         # the handle is unaffected
+    s.set_launch(blocks=(8, 8, 8, 8))      # shapes are still applied without timing
+    b = outputs(s)
+    same_partition_as_default(a, b, False)
+    s.close()
+    with pytest.raises(pbe.PBEError) as e:
+        pbe.Solver(prob, autotune=True)
+    assert e.value.code == pbe.PBE_EUNSUPPORTED
 
 
 def same_partition_as_default(a, b, pairs):
