@@ -188,6 +188,20 @@ int pbe_mlp_forward(const float *blob, int32_t precision, int32_t n, const doubl
 int pbe_mlp_vjp(const float *blob, int32_t precision, int32_t n, const double *z, const double *ybar, double *gw,
                 void *hip_stream);
 
+/* pbe_mlp_vjp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight training loops, harnesses that forbid hipMalloc): the
+ * same result, bitwise, for n <= PBE_MLP_VJP_NOALLOC_MAX_ROWS rows (PBE_EINVAL
+ * beyond), with no hipMalloc, hipFree or other allocation.  Its scratch is a
+ * fixed device array of the library (about 9.6 MB: blob copy, packed
+ * operands, staged rows, one partial gradient per 16-row tile), one per GPU,
+ * held until the process ends.  Every call on a GPU uses that GPU's array, so
+ * calls that overlap on one GPU (other host threads, or streams that are not
+ * ordered) race; each call blocks until its result is in gw.  z, ybar, gw are
+ * device pointers on the current device ordered on hip_stream; blob is host. */
+#define PBE_MLP_VJP_NOALLOC_MAX_ROWS 4096
+int pbe_mlp_vjp_noalloc(const float *blob, int32_t precision, int32_t n, const double *z, const double *ybar,
+                        double *gw, void *hip_stream);
+
 /* One Adam step (Kingma and Ba; the optimiser of Sec. 4.1 / App. C) on device
  * arrays of n floats: w -= lr * mhat / (sqrt(vhat) + eps) with the moment
  * estimates m, v updated from the gradient g (device, double) and bias

@@ -27,7 +27,8 @@ NGRAD = 5
 # every entry point of include/pbe.h
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
            "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_set_launch", "pbe_destroy", "pbe_strerror",
-           "pbe_last_kernel_ms", "pbe_rate_log", "pbe_mlp_vjp"]
+           "pbe_last_kernel_ms", "pbe_rate_log", "pbe_mlp_vjp", "pbe_mlp_vjp_noalloc"]
+MLP_VJP_NOALLOC_MAX_ROWS = 4096
 MLP_NW, MLP_NC = 4546, 18
 MLP_BF16, MLP_FP64 = 0, 1
 
@@ -88,6 +89,7 @@ def lib():
         L.pbe_last_kernel_ms.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.pbe_rate_log.argtypes = [vp, C.c_int32, vp]
         L.pbe_mlp_vjp.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
+        L.pbe_mlp_vjp_noalloc.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("pbe_destroy", "pbe_strerror"):
                 getattr(L, name).restype = C.c_int
@@ -269,9 +271,10 @@ def mlp_forward(blob, precision: int, x):
     return y, dy
 
 
-def mlp_vjp(blob, precision: int, z, ybar):
+def mlp_vjp(blob, precision: int, z, ybar, noalloc: bool = False):
     """Weight gradient sum_r (dy/dW at z_r)^T ybar_r of the closure network over rows of
-    normalised inputs z[n, 3] and output cotangents ybar[n, 2]: a [MLP_NW] device tensor."""
+    normalised inputs z[n, 3] and output cotangents ybar[n, 2]: a [MLP_NW] device tensor.
+    noalloc: use pbe_mlp_vjp_noalloc (no device allocation in the library; n <= 4096)."""
     import torch
     b = _arr(blob, np.float32)
     assert b.size == MLP_NW + MLP_NC
@@ -281,8 +284,9 @@ def mlp_vjp(blob, precision: int, z, ybar):
     assert zt.shape[0] == yt.shape[0]
     gw = torch.empty(MLP_NW, dtype=torch.float64, device=dev)
     st = torch.cuda.current_stream()
-    _check(lib().pbe_mlp_vjp(b.ctypes.data_as(C.POINTER(C.c_float)), precision, zt.shape[0], _ptr(zt), _ptr(yt),
-                             _ptr(gw), C.c_void_p(st.cuda_stream)), "pbe_mlp_vjp")
+    fn = lib().pbe_mlp_vjp_noalloc if noalloc else lib().pbe_mlp_vjp
+    _check(fn(b.ctypes.data_as(C.POINTER(C.c_float)), precision, zt.shape[0], _ptr(zt), _ptr(yt), _ptr(gw),
+              C.c_void_p(st.cuda_stream)), "pbe_mlp_vjp_noalloc" if noalloc else "pbe_mlp_vjp")
     return gw
 
 

@@ -108,9 +108,10 @@ __global__ __launch_bounds__(64) void k_closure_forward(ClosureDev cd, int n, co
     }
 }
 
-// rows[r] = (z0, z1, z2, ybar0, ybar1) for r < n, zero rows up to row_cap
+// rows[r] = (z0, z1, z2, ybar0, ybar1) for r < n, zero rows up to row_cap; *steps = n
 __global__ void k_stage_rows(int n, int row_cap, const double* __restrict__ z, const double* __restrict__ ybar,
-                             double* __restrict__ rows) {
+                             double* __restrict__ rows, int32_t* __restrict__ steps) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *steps = n;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < row_cap; r += gridDim.x * blockDim.x) {
         double* q = rows + (size_t)r * 5;
         const bool in = r < n;
@@ -443,9 +444,10 @@ hipError_t launch_closure_grad(const ClosureDev& cd, const double* rows, const i
     return hipGetLastError();
 }
 
-hipError_t launch_stage_rows(int n, int row_cap, const double* z, const double* ybar, double* rows, hipStream_t st) {
+hipError_t launch_stage_rows(int n, int row_cap, const double* z, const double* ybar, double* rows, int32_t* steps,
+                             hipStream_t st) {
     const int blocks = std::max(1, std::min(1024, (row_cap + 255) / 256));
-    hipLaunchKernelGGL(k_stage_rows, dim3(blocks), dim3(256), 0, st, n, row_cap, z, ybar, rows);
+    hipLaunchKernelGGL(k_stage_rows, dim3(blocks), dim3(256), 0, st, n, row_cap, z, ybar, rows, steps);
     return hipGetLastError();
 }
 

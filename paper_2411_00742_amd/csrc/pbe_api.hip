@@ -760,6 +760,48 @@ int tune_handle(pbe_handle* h, int trial_steps, bool use_cache, pbe_tuning* out)
 }
 }  // namespace
 
+// ----------------------------------------------------------------- no-allocation weight gradient
+// pbe_mlp_vjp_noalloc keeps its scratch (blob copy, packed operands, staged
+// rows, row count, per-wave partial gradients) in this fixed device array.
+// Every GPU the library runs on holds its own copy, at its own address, until
+// the process ends; host code only ever uses the address hipGetSymbolAddress
+// returns for the current device.
+namespace {
+constexpr size_t kNaBlob = 18432;                                            // >= 4 * (PBE_MLP_NW + PBE_MLP_NC)
+constexpr size_t kNaPack = 65536;                                            // closure_pack_bytes()
+constexpr size_t kNaRows = sizeof(double) * 5 * PBE_MLP_VJP_NOALLOC_MAX_ROWS;
+constexpr size_t kNaSteps = 256;
+constexpr int kNaPartialMax = PBE_MLP_VJP_NOALLOC_MAX_ROWS / 16;              // one wave per 16-row tile
+constexpr size_t kNaPartials = sizeof(double) * PBE_MLP_NW * kNaPartialMax;
+constexpr size_t kNoAllocScratchBytes = kNaBlob + kNaPack + kNaRows + kNaSteps + kNaPartials;
+static_assert(kNaBlob >= sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), "blob slot");
+static_assert(kNaBlob % 256 == 0 && kNaPack % 256 == 0 && kNaRows % 256 == 0 && kNaSteps % 256 == 0,
+              "every part of the scratch starts 256-byte aligned");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // device address of `scratch`, per device ordinal
+
+// Address of this device's scratch array, looked up once per device (with
+// that device current) on the first call there.
+int scratch_on_current_device(unsigned char** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return PBE_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PBE_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return PBE_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* pbe_strerror(int code) {
@@ -1142,16 +1184,49 @@ int pbe_mlp_vjp(const float* blob, int32_t precision, int32_t n, const double* z
     }
     ClosureDev cd{};
     int rc = PBE_OK;
-    const int32_t steps = n;
     if (hipMemcpy(d_blob, blob, sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_steps, &steps, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         pack_closure(d_blob, d_pack, precision, &cd, st) != hipSuccess ||
-        launch_stage_rows(n, row_cap, z, ybar, d_rows, st) != hipSuccess ||
+        launch_stage_rows(n, row_cap, z, ybar, d_rows, d_steps, st) != hipSuccess ||
         launch_closure_grad(cd, d_rows, d_steps, 1, row_cap, d_partial, n_partial, gw, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         rc = PBE_EDEVICE;
     m.release();
     return rc;
+}
+
+int pbe_mlp_vjp_noalloc(const float* blob, int32_t precision, int32_t n, const double* z, const double* ybar,
+                        double* gw, void* hip_stream) {
+    if (!blob || n < 0 || !gw || (n > 0 && (!z || !ybar))) return PBE_EINVAL;
+    if (n > PBE_MLP_VJP_NOALLOC_MAX_ROWS) return PBE_EINVAL;
+    if (precision != PBE_MLP_BF16 && precision != PBE_MLP_FP64) return PBE_EINVAL;
+    for (int i = 0; i < PBE_MLP_NW + PBE_MLP_NC; ++i)
+        if (!is_finite(blob[i])) return PBE_EINVAL;
+    if (closure_pack_bytes() > kNaPack) return PBE_EDEVICE;
+    unsigned char* base = nullptr;
+    const int rc0 = scratch_on_current_device(&base);
+    if (rc0 != PBE_OK) return rc0;
+    float* d_blob = reinterpret_cast<float*>(base);
+    void* d_pack = base + kNaBlob;
+    double* d_rows = reinterpret_cast<double*>(base + kNaBlob + kNaPack);
+    int32_t* d_steps = reinterpret_cast<int32_t*>(base + kNaBlob + kNaPack + kNaRows);
+    double* d_partial = reinterpret_cast<double*>(base + kNaBlob + kNaPack + kNaRows + kNaSteps);
+    // the same tiling as pbe_mlp_vjp (so the same partial sums in the same order)
+    const int row_cap = std::max(16, (n + 15) / 16 * 16);
+    const int n_partial = std::min(1024, row_cap / 16);
+    if (n_partial > kNaPartialMax) return PBE_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // every scratch word the kernels read is written first in this call: the
+    // blob and the packed operands, all row_cap staged rows, the row count,
+    // and each wave's whole partial gradient
+    ClosureDev cd{};
+    if (hipMemcpyAsync(d_blob, blob, sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        pack_closure(d_blob, d_pack, precision, &cd, st) != hipSuccess ||
+        launch_stage_rows(n, row_cap, z, ybar, d_rows, d_steps, st) != hipSuccess ||
+        launch_closure_grad(cd, d_rows, d_steps, 1, row_cap, d_partial, n_partial, gw, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return PBE_EDEVICE;
+    return PBE_OK;
 }
 
 int pbe_adam(float* w, float* m, float* v, const double* g, int32_t n, int32_t step, float lr, float beta1,

@@ -180,7 +180,8 @@ hipError_t pack_closure(const float* d_blob, void* mem, int precision, ClosureDe
 hipError_t launch_closure_forward(const ClosureDev& cd, int n, const double* x, double* y, double* dy, hipStream_t st);
 hipError_t launch_closure_grad(const ClosureDev& cd, const double* rows, const int32_t* steps, int n_sims,
                                int row_cap, double* partial, int n_blocks, double* out, hipStream_t st);
-hipError_t launch_stage_rows(int n, int row_cap, const double* z, const double* ybar, double* rows, hipStream_t st);
+hipError_t launch_stage_rows(int n, int row_cap, const double* z, const double* ybar, double* rows, int32_t* steps,
+                             hipStream_t st);
 hipError_t launch_adam(float* w, float* m, float* v, const double* g, int n, int step, float lr, float b1, float b2,
                        float eps, hipStream_t st);
 
