@@ -9,10 +9,16 @@ cell advanced one full SSP-RK3 step.
 
 Beside the main figure the JSON line carries:
   plain_single_sim   the same simulations solved one per launch (the plain path)
-  roofline           the dominant kernel against the FP64 vector peak (ALU bound:
-                     the density stays in registers, HBM traffic is negligible)
+  roofline           the dominant kernel (the four concurrent 1D class kernels of
+                     one solve) against the HBM roof: algorithmic bytes of the
+                     streaming form of the step (16 B per cell-update: read f^n,
+                     write f^{n+1}) over the kernel span; its `fp64` field gives the
+                     same span against the FP64 vector peak (the density stays in
+                     registers, so measured HBM traffic, `traffic`, is far below)
   cpu_baseline       the FP64 CPU oracle on a sample of the same workload
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --calibrate-copy MIB   (a plain device copy of known size, for
+                                               calibrating the HBM traffic counters)
 """
 from __future__ import annotations
 
@@ -220,6 +226,28 @@ def fvm2d_leg(steps: int):
                 cell_updates_per_solve=cu, ms_per_solve=1e3 * el)
 
 
+def calibrate_copy(mib: int):
+    """A plain device-to-device copy of known size: the HBM counters (FETCH_SIZE, WRITE_SIZE) read
+    over it, divided by the bytes it must move, give the scale applied to the solver kernels'
+    readings.  Also prints the copy bandwidth measured with events."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(3):
+        ev[0].record()
+        b.copy_(a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    gbs = 2 * n * 8 / (min(ms) * 1e-3) / 1e9
+    print(json.dumps({"copy_mib": mib, "kib_read_per_copy": mib * 1024, "kib_written_per_copy": mib * 1024,
+                      "copies": 3, "best_ms": min(ms), "copy_GBps": gbs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,7 +262,12 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first (pbe_tune)")
     ap.add_argument("--steps-closure", type=int, default=3)
     ap.add_argument("--steps-2d", type=int, default=2)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the batched solver shards "
               f"independent simulations and is run per GPU", file=sys.stderr)
@@ -302,13 +335,17 @@ def main():
     plain = plain_cells / plain_s
     log(f"[bench] plain single-sim path: {plain:.4e} cell-updates/s over {len(pick)} sims")
 
-    achieved = FLOP_PER_CELL_UPDATE * cell_updates / (avg_kernel_ms * 1e-3) / 1e12
-    roofline = dict(bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=measured_traffic(),
+    hbm_gbs = HBM_BYTES_PER_CELL_UPDATE * cell_updates / (avg_kernel_ms * 1e-3) / 1e9
+    tflops = FLOP_PER_CELL_UPDATE * cell_updates / (avg_kernel_ms * 1e-3) / 1e12
+    roofline = dict(bound="hbm", achieved=hbm_gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm_gbs / HBM_PEAK_GBS,
+                    traffic=measured_traffic(),
+                    traffic_source="profiles/fvm1d_batched4096_hbm_traffic.md (rocprofv3 FETCH_SIZE + WRITE_SIZE "
+                                   "per solve, copy-calibrated; null once the kernel sources changed)",
                     kernel="k_fvm1d (4 concurrent lane-count classes, one captured graph)",
-                    flop_per_cell_update=FLOP_PER_CELL_UPDATE,
-                    hbm_equivalent_frac=HBM_BYTES_PER_CELL_UPDATE * cell_updates / (avg_kernel_ms * 1e-3)
-                    / (HBM_PEAK_GBS * 1e9))
+                    bytes_per_cell_update=HBM_BYTES_PER_CELL_UPDATE, cell_updates_per_launch=cell_updates,
+                    span_ms=avg_kernel_ms,
+                    fp64=dict(bound="alu", achieved=tflops, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=tflops / FP64_VECTOR_PEAK_TFLOPS, flop_per_cell_update=FLOP_PER_CELL_UPDATE))
 
     result = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
