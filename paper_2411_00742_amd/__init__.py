@@ -152,6 +152,7 @@ class Solver:
         self.ckpt_every = ckpt_every
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.generation = 0   # bumped by every call that replaces the recorded solve
         st, keep = make_problem_struct(prob, ckpt_every, record_f, True, max_steps, autotune, record_rates)
         self._h = C.c_void_p()
         _check(lib().pbe_create(C.byref(st), C.c_void_p(self.stream.cuda_stream), C.byref(self._h)), "pbe_create")
@@ -172,12 +173,14 @@ class Solver:
     def solve(self, out=None):
         """Solve every simulation from the initial condition; returns dict of device tensors."""
         o = out if out is not None else self._outputs()
+        self.generation += 1
         _check(lib().pbe_solve(self._h, _ptr(o["f"]), _ptr(o["mom"]), _ptr(o["C"]), _ptr(o["steps"]),
                                _ptr(o["status"])), "pbe_solve")
         return o
 
     def step(self, n_steps: int) -> int:
         n_active = C.c_int32()
+        self.generation += 1
         _check(lib().pbe_step(self._h, n_steps, C.byref(n_active)), "pbe_step")
         return n_active.value
 
@@ -188,9 +191,11 @@ class Solver:
         return o
 
     def reset(self):
+        self.generation += 1
         _check(lib().pbe_reset(self._h), "pbe_reset")
 
     def set_par(self, par):
+        self.generation += 1
         p = _arr(par, np.float64)
         assert p.shape == (self.S, NPAR)
         _check(lib().pbe_set_par(self._h, p.ctypes.data_as(_dp)), "pbe_set_par")
@@ -207,6 +212,7 @@ class Solver:
 
     def set_mlp(self, w):
         """New closure weights: a float32 device tensor (or array) of MLP_NW values."""
+        self.generation += 1
         t = self.torch
         w = t.as_tensor(w, dtype=t.float32).to(self.device).contiguous()
         assert w.numel() == MLP_NW
@@ -329,11 +335,17 @@ def _autograd_function():
             solver.set_par(par)
             out = solver.solve()
             ctx.solver = solver
+            ctx.generation = solver.generation
             ctx.par_device = par5.device
             return out["f"], out["mom"], out["C"]
 
         @staticmethod
         def backward(ctx, gf, gmom, gC):
+            # pbe_grad differentiates the handle's last solve: a later solve on the same
+            # solver (another forward before this backward) has replaced it
+            if ctx.solver.generation != ctx.generation:
+                raise RuntimeError("PBESolve.backward: the solver ran another solve after this forward; "
+                                   "use one Solver per differentiable solve that is still to be back-propagated")
             g = ctx.solver.grad(gf, gmom, gC)
             return g.to(ctx.par_device), None
 
