@@ -211,6 +211,7 @@ def fvm2d_leg(steps: int):
     from paper_2411_00742_amd import workloads as W
     prob = W.shape_2d()
     solver = pbe.Solver(prob)
+    tuning = solver.tune(trial_steps=30)   # tile height chosen by the autotuner (pbe_tune)
     out = solver.solve()
     torch.cuda.synchronize()
     st = out["steps"].cpu().numpy().astype(np.int64)
@@ -223,7 +224,9 @@ def fvm2d_leg(steps: int):
     el = (time.perf_counter() - t0) / steps
     solver.close()
     return dict(value=cu / el, unit="cell-updates/s", n_sims=prob.n_sims, cells=int(cells.sum()),
-                cell_updates_per_solve=cu, ms_per_solve=1e3 * el)
+                cell_updates_per_solve=cu, ms_per_solve=1e3 * el,
+                hbm_frac_32B=32.0 * cu / el / (HBM_PEAK_GBS * 1e9),
+                tile_rows=tuning["seg_2d"], tuning_ms={"best": tuning["best_ms"], "default": tuning["default_ms"]})
 
 
 def calibrate_copy(mib: int):

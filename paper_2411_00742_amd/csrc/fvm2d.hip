@@ -1,24 +1,33 @@
 // 2D size-and-shape PBE (length L1 x width L2), Godunov dimensional splitting
-// (paper Sec. 2.1: the update of Eq. (8) applied along each length in turn),
-// SSP-RK3 per sweep, FP64, many simulations per launch (gfx950).
+// (paper Sec. 2.1: the update of Eq. (8) applied along each length in turn,
+// L1 first), SSP-RK3 (or the one-step form of Eq. (8)) per sweep, FP64, many
+// simulations per launch (gfx950).
 //
-// One global step = three launches (captured in a graph by the host):
-//   k_rows2d  L1 sweep: one wavefront per row, the row in registers exactly as
-//             the 1D kernel holds a simulation (same stage code), in place; the
-//             row passes through LDS on its way in and out so that every
-//             global access is a contiguous 512-byte wave access;
-//   k_cols2d  L2 sweep: a wavefront owns 64 adjacent columns and a segment of
-//             rows; each lane marches down its column with the three SSP-RK3
-//             stages pipelined in registers (stage s lags s rows), so every
-//             load and store is a coalesced 512-byte row segment and no lane
-//             talks to another.  Segments start 6 rows early (the stencil halo
-//             of three stages); the sweep reads one buffer and writes the other,
-//             with eight row loads in flight per wave.
-//             It also sums the moments of the swept state per block;
-//   k_final2d one wavefront per simulation: reduces the block moments in a fixed
-//             order, applies the solute balance (Eq. (9) with mu_{1,2}), records
-//             samples, and computes the next step's rates, CFL step (SI Eq. (S3))
-//             and the corner nucleation ghosts.
+// One global step = two launches (captured in a graph by the host):
+//   k_step2d  both sweeps in one pass over the state.  A wavefront owns a tile
+//             of TW columns x seg rows of one simulation and marches down its
+//             rows: each input row is loaded once (64 consecutive doubles, a
+//             coalesced 512-byte access), swept along L1 across the lanes (one
+//             cell per lane, neighbours by DPP; the tile is widened by the
+//             stencil halo of the three stages, 6 cells left and 3 right, whose
+//             lanes are recomputed by the neighbouring tile), and the swept
+//             value enters the lane's L2 pipeline: the three SSP-RK3 stages
+//             along the column held in registers, stage s lagging s rows.  The
+//             finished row (3 rows behind the input) goes to the other state
+//             buffer.  So the state crosses HBM once per step (read f^n, write
+//             f^{n+1}) instead of once per sweep.  Tiles start 6 rows early
+//             and end 2 rows late (the L2 halo).  The tile also sums the
+//             moments of the new state and the number that leaves through
+//             L1_max and L2_max.
+//   k_final2d one wavefront per simulation: reduces the tile partials in a
+//             fixed order, applies the solute balance (Eq. (9) with mu_{1,2}),
+//             records samples, and computes the next step's rates, CFL step
+//             (SI Eq. (S3)) and the corner nucleation ghosts.  (Folding this
+//             into the tile kernel with a last-tile ticket needs a device-scope
+//             release per tile, which writes back the L2 of the tile's XCD:
+//             three times slower in total.)
+#include <type_traits>
+
 #include "fvm1d_device.h"
 #include "pbe_internal.h"
 
@@ -27,173 +36,95 @@ namespace {
 
 using namespace dev;
 
-// The row moves between HBM and registers through LDS: the wave reads and
-// writes the row as 64 consecutive doubles per instruction (element e = lane +
-// 64 i of the right-aligned row), and each lane takes its K consecutive cells
-// from LDS.  Element e sits at (e / K) * P + e % K with P = K rounded up to odd,
-// so the K-strided per-lane reads fall in distinct banks.
-template <int K>
-__device__ __forceinline__ void row_sweep(const Fvm2dArgs& a, int parity, int s, int j, double* lds) {
-    const int lane = threadIdx.x;
-    const int n1 = uniform(a.n1[s]);
-    const int pad = 64 * K - n1;
-    LaneGeom g;
-    g.xb = (double)(lane * K - pad);
-    g.gdL = 0.0;   // size-independent growth along each axis
-    g.npad = min(max(pad - lane * K, 0), K);
-    const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
-    double* row = a.buf[parity] + o + (int64_t)j * n1;
-    // nucleation: row 0 receives half the corner source through its L1 = 0 face
-    const double ghost = j == 0 ? uniform(a.gh1[s]) : 0.0;
-    const double c = uniform(a.c1[s]);
-    constexpr int P = K | 1;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int e = lane + 64 * i;
-        const int cell = e - pad;   // < n1 always; < 0 in the pad
-        lds[(e / K) * P + e % K] = cell >= 0 ? row[cell] : 0.0;
-    }
-    __syncthreads();
-    double u[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = lds[lane * P + k];
-    (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, c, ghost);
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[lane * P + k] = u[k];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int e = lane + 64 * i;
-        const int cell = e - pad;
-        if (cell >= 0) row[cell] = lds[(e / K) * P + e % K];
-    }
-}
-
-template <int KLO>
-__global__ __launch_bounds__(64) void k_rows2d(Fvm2dArgs a, int parity, int begin) {
-    __shared__ double lds[64 * ((KLO + 7) | 1)];
-    const int r = begin + (int)blockIdx.x;
-    const int s = uniform(a.row_sim[r]);
-    if (!uniform(a.active[s])) return;
-    const int j = uniform(a.row_j[r]);
-    const int K = uniform((a.n1[s] + 63) >> 6);
-    switch (K - KLO) {
-        case 0: row_sweep<KLO + 0>(a, parity, s, j, lds); break;
-        case 1: row_sweep<KLO + 1>(a, parity, s, j, lds); break;
-        case 2: row_sweep<KLO + 2>(a, parity, s, j, lds); break;
-        case 3: row_sweep<KLO + 3>(a, parity, s, j, lds); break;
-        case 4: row_sweep<KLO + 4>(a, parity, s, j, lds); break;
-        case 5: row_sweep<KLO + 5>(a, parity, s, j, lds); break;
-        case 6: row_sweep<KLO + 6>(a, parity, s, j, lds); break;
-        case 7: row_sweep<KLO + 7>(a, parity, s, j, lds); break;
-        default: break;
-    }
-}
-
-// One SSP-RK3 stage running down a column: holds the last two inputs and the
-// face value below them; fed the input at row r+1 it emits the stage output at row r.
-struct ColStage {
-    double im1, i0, Fm1;
+// Stencil halo of a sweep: an updated cell depends on 2 cells to its left and
+// 1 to its right per stage.
+template <int SCHEME>
+struct Halo2d {
+    static constexpr int stages = SCHEME == PBE_SCHEME_SSPRK3 ? 3 : 1;
+    static constexpr int left = 2 * stages, right = stages;
+    static constexpr int width = 64 - left - right;   // output columns of a tile
 };
-__device__ __forceinline__ double col_face(double a, double b, double x) {
-    return b + half_limited_slope(b - a, x - b);
+
+// Neighbour values across the wave with no fill: lanes without a source read
+// 0 (DPP bound_ctrl).  Only halo lanes of a tile ever read that value.
+__device__ __forceinline__ double from_left(double v) { return dpp_src<0x138>(v); }    // wave_shr:1
+__device__ __forceinline__ double from_right(double v) { return dpp_src<0x130>(v); }   // wave_shl:1
+
+// L1 sweep of one row across the wave, one cell per lane (stage inputs u,
+// faces H = face value right of each lane's cell).  In tiles that reach past
+// the domain (EXT), lanes left of it hold the row's inflow ghost and lanes
+// past L1_max hold 0, and are put back to those values after every stage.
+// Returns the new value; *hN receives the stage-weighted value of this lane's
+// right face (the outflow face for the lane at n1 - 1).
+template <int SCHEME, bool EXT>
+__device__ __forceinline__ double row_sweep_tile(double u, double c, double ghost, bool left_ext, bool right_ext,
+                                                 double* hN) {
+    auto ext = [&](double v) { return EXT ? (left_ext ? ghost : (right_ext ? 0.0 : v)) : v; };
+    if constexpr (SCHEME == PBE_SCHEME_LW_TVD) {
+        const double H = face_value<SCHEME>(from_left(u), u, from_right(u), 1.0, c);
+        const double v = u + c * (from_left(H) - H);
+        *hN = H;
+        return ext(v);
+    } else {
+        const double u0 = u;
+        double h[3];
+#pragma unroll
+        for (int st = 0; st < 3; ++st) {
+            const double H = face_value<SCHEME>(from_left(u), u, from_right(u), 1.0, c);
+            const double v = u + c * (from_left(H) - H);
+            u = st == 0 ? v : (st == 1 ? 0.75 * u0 + 0.25 * v : (1.0 / 3.0) * u0 + (2.0 / 3.0) * v);
+            u = ext(u);
+            h[st] = H;
+        }
+        *hN = fma(h[0] + h[1], 1.0 / 6.0, (2.0 / 3.0) * h[2]);
+        return u;
+    }
 }
+
+// One stage running down a column: holds the last two inputs and the face
+// value below them; fed the input at row r+1 it emits the stage output at row
+// r and *F the face value between rows r and r+1.  EDGE: r may lie outside
+// [0, n2) (ghost rows below L2 = 0 hold the ghost, nothing past L2_max).
+struct ColStage {
+    double a, i0, Fm1;   // slope i0 - (row below i0), row i0, face value below i0
+};
+template <int SCHEME, bool EDGE>
 __device__ __forceinline__ double col_feed(ColStage& st, double x, double c, double u0r, double wa, double wb,
-                                           bool first, int r, int n2, double ghost) {
-    const double F = col_face(st.im1, st.i0, x);
+                                           bool first, int r, int n2, double ghost, double* F_out) {
+    const double b = x - st.i0;
+    const double F = face_value_ab<SCHEME>(st.a, b, st.i0, 1.0, c);
     const double v = st.i0 + c * (st.Fm1 - F);
     double out = first ? v : wa * u0r + wb * v;
-    out = r < 0 ? ghost : (r >= n2 ? 0.0 : out);   // ghost rows below L2 = 0, nothing past L2_max
-    st.im1 = st.i0;
+    if (EDGE) out = r < 0 ? ghost : (r >= n2 ? 0.0 : out);
+    st.a = b;
     st.i0 = x;
     st.Fm1 = F;
+    *F_out = F;
     return out;
 }
 
-constexpr int kColAhead = 8;   // row loads in flight per wave in the column sweep
+constexpr int kColAhead = 8;   // row loads in flight per wave
 
-__global__ __launch_bounds__(64) void k_cols2d(Fvm2dArgs a, int parity) {
-    const int b = blockIdx.x;
-    const int s = uniform(a.cb_sim[b]);
-    if (!uniform(a.active[s])) return;
-    const int lane = threadIdx.x;
-    const int n1 = uniform(a.n1[s]), n2 = uniform(a.n2[s]);
-    const int col0 = uniform(a.cb_col0[b]), row0 = uniform(a.cb_row0[b]);
-    const int row1 = min(row0 + a.seg, n2);
-    const int i = col0 + lane;
-    const bool valid = i < n1;
-    const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
-    const double* src = a.buf[parity] + o + (valid ? i : 0);
-    double* dst = a.buf[parity ^ 1] + o + (valid ? i : 0);
-    const double c = uniform(a.c2[s]);
-    // column 0 receives the other half of the corner source through its L2 = 0 face
-    const double ghost = i == 0 ? uniform(a.gh2[s]) : 0.0;
-    const double d1 = uniform(a.L1[s]) / n1, d2 = uniform(a.L2[s]) / n2;
-    const double L1c = (i + 0.5) * d1;
-
-    ColStage s1{0.0, 0.0, 0.0}, s2{0.0, 0.0, 0.0}, s3{0.0, 0.0, 0.0};
-    double u0_1 = 0.0, u0_2 = 0.0, u0_3 = 0.0;   // f^n at rows R-1, R-2, R-3
-    double m00 = 0.0, m10 = 0.0, m01 = 0.0, m12 = 0.0;
-    // Input rows are loaded kColAhead rows ahead of their use into a ring, so
-    // a wave keeps that many row loads in flight instead of waiting on each
-    // one; rows outside [0, n2) read a clamped in-range row and are replaced
-    // by the ghost (below L2 = 0) or 0 (past L2_max).
-    const int R0 = row0 - 6, R1 = row1 + 2;
-    // (the ring holds the raw loads; the substitution is applied when a row is
-    // consumed, so nothing waits on a load before its turn)
-    auto load_row = [&](int R) -> double { return src[(int64_t)min(max(R, 0), n2 - 1) * n1]; };
-    double ring[kColAhead];
-#pragma unroll
-    for (int j = 0; j < kColAhead; ++j) ring[j] = load_row(R0 + j);
-    for (int Rb = R0; Rb <= R1; Rb += kColAhead) {
-#pragma unroll
-        for (int j = 0; j < kColAhead; ++j) {
-            const int R = Rb + j;
-            if (R > R1) break;
-            const double x = R < 0 ? ghost : (R >= n2 || !valid ? 0.0 : ring[j]);
-            ring[j] = load_row(R + kColAhead);
-            const double v1 = col_feed(s1, x, c, 0.0, 0.0, 1.0, true, R - 1, n2, ghost);
-            const double v2 = col_feed(s2, v1, c, u0_2, 0.75, 0.25, false, R - 2, n2, ghost);
-            const double v3 = col_feed(s3, v2, c, u0_3, 1.0 / 3.0, 2.0 / 3.0, false, R - 3, n2, ghost);
-            const int r = R - 3;
-            if (r >= row0 && r < row1) {
-                if (valid) dst[(int64_t)r * n1] = v3;
-                const double f = valid ? v3 : 0.0;
-                const double L2c = (r + 0.5) * d2;
-                m00 += f;
-                m10 = fma(L1c, f, m10);
-                m01 = fma(L2c, f, m01);
-                m12 = fma(L1c * L2c * L2c, f, m12);
-            }
-            u0_3 = u0_2;
-            u0_2 = u0_1;
-            u0_1 = x;
-        }
-    }
-    const double dA = d1 * d2;
-    m00 = wave_sum(m00) * dA;
-    m10 = wave_sum(m10) * dA;
-    m01 = wave_sum(m01) * dA;
-    m12 = wave_sum(m12) * dA;
-    if (lane == 0) {
-        double* p = a.part + (int64_t)b * 4;
-        p[0] = m00; p[1] = m10; p[2] = m01; p[3] = m12;
-    }
+// Block b -> tile: the hardware hands consecutive blocks to the 8 XCDs in
+// turn, so blocks b, b + 8, b + 16, ... share an XCD (and its L2).  They get
+// consecutive tiles, which read each other's halo rows and columns.
+__device__ __forceinline__ int tile_of_block(int b, int n_blocks) {
+    const int per_xcd = n_blocks >> 3;   // n_blocks is a multiple of 8
+    return (b & 7) * per_xcd + (b >> 3);
 }
 
 // Per simulation: finish the step (init = 0) or start the solve (init = 1), then
 // prepare the next step's rates, step size and ghosts.
-__global__ __launch_bounds__(64) void k_final2d(Fvm2dArgs a, int init) {
-    const int s = blockIdx.x;
+__device__ void finalize_sim(const Fvm2dArgs& a, int s, int init) {
     const int lane = threadIdx.x;
-    const Process p{a.law, PBE_SCHEME_SSPRK3, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
+    const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
     const double* P = a.par + (size_t)s * PBE_NPAR;
     const SimParams q = load_params(P);
     const double kg2 = uniform(P[PBE_P_KG2]), g2 = uniform(P[PBE_P_G2]);
     const int n1 = uniform(a.n1[s]), n2 = uniform(a.n2[s]);
     const double d1 = uniform(a.L1[s]) / n1, d2 = uniform(a.L2[s]) / n2;
     const int ns = a.n_samples;
-    double C, t;
+    double C, t, out, mu0 = 0.0;
     int step, next, status;
     if (init) {
         // volume moment of the initial state (midpoint rule, SI Eq. (S5))
@@ -209,20 +140,23 @@ __global__ __launch_bounds__(64) void k_final2d(Fvm2dArgs a, int init) {
         m12 = wave_sum(m12) * d1 * d2;
         C = uniform(a.C0[s]);
         t = 0.0;
+        out = 0.0;
         step = 0; next = 0; status = 0;
         if (lane == 0) a.mu12[s] = m12;
     } else {
         if (!uniform(a.active[s])) return;
-        C = uniform(a.C[s]); t = uniform(a.t[s]);
+        C = uniform(a.C[s]); t = uniform(a.t[s]); out = uniform(a.outflow[s]);
         step = uniform(a.step[s]); next = uniform(a.next[s]); status = uniform(a.status[s]);
-        // block moments of the new state, summed in block order
-        double m[4] = {0.0, 0.0, 0.0, 0.0};
+        // tile moments of the new state and outflow, summed in tile order
+        double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         const int b0 = uniform(a.cb_first[s]), b1 = uniform(a.cb_first[s + 1]);
         for (int bb = b0 + lane; bb < b1; bb += 64)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m[k] += a.part[(int64_t)bb * 4 + k];
+            for (int k = 0; k < 5; ++k) m[k] += a.part[(int64_t)bb * 5 + k];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) m[k] = wave_sum(m[k]);
+        for (int k = 0; k < 5; ++k) m[k] = wave_sum(m[k]);
+        out = uniform(out + m[4]);
+        mu0 = m[0];
         // discrete solute balance, Eq. (9), with the volume moment mu_{1,2}
         C = uniform(C - p.alpha * (m[3] - uniform(a.mu12[s])));
         const bool hit = uniform(a.hit[s]) != 0;
@@ -250,6 +184,8 @@ __global__ __launch_bounds__(64) void k_final2d(Fvm2dArgs a, int init) {
     int hit = 0;
     if (!(t < p.t_end) || (status & PBE_SIM_NONFINITE)) {
         active = 0;
+        // crystals that left through L1_max or L2_max (counted, not returned to the solution)
+        if (!init && out > 1e-12 * fmax(mu0, 1e-300)) status |= PBE_SIM_OUTFLOW;
     } else if (step >= a.step_cap) {
         status |= PBE_SIM_STEPCAP;
         active = 0;
@@ -273,9 +209,141 @@ __global__ __launch_bounds__(64) void k_final2d(Fvm2dArgs a, int init) {
         gh2 = r.G2 > 0.0 ? r.B / (2.0 * d1 * r.G2) : 0.0;
     }
     if (lane == 0) {
-        a.C[s] = C; a.t[s] = t; a.step[s] = step; a.next[s] = next; a.status[s] = status;
+        a.C[s] = C; a.t[s] = t; a.step[s] = step; a.next[s] = next; a.status[s] = status; a.outflow[s] = out;
         a.active[s] = active; a.dt[s] = dt; a.hit[s] = hit;
         a.c1[s] = c1; a.c2[s] = c2; a.gh1[s] = gh1; a.gh2[s] = gh2;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_final2d(Fvm2dArgs a, int init) { finalize_sim(a, blockIdx.x, init); }
+
+template <int SCHEME>
+__global__ __launch_bounds__(64) void k_step2d(Fvm2dArgs a, int parity) {
+    using H = Halo2d<SCHEME>;
+    constexpr bool RK = SCHEME == PBE_SCHEME_SSPRK3;
+    const int b = tile_of_block((int)blockIdx.x, (int)gridDim.x);
+    if (b >= a.n_cb) return;
+    const int s = uniform(a.cb_sim[b]);
+    if (!uniform(a.active[s])) return;
+    const int lane = threadIdx.x;
+    const int n1 = uniform(a.n1[s]), n2 = uniform(a.n2[s]);
+    const int c0 = uniform(a.cb_col0[b]), r0 = uniform(a.cb_row0[b]);
+    const int r1 = min(r0 + a.seg, n2);
+    const int col = c0 - H::left + lane;
+    const bool left_ext = col < 0, right_ext = col >= n1;
+    // a tile whose lanes all lie inside the domain needs no exterior masks
+    const bool interior = c0 - H::left >= 0 && c0 - H::left + 63 < n1;
+    const bool out_lane = lane >= H::left && lane < H::left + H::width && !right_ext;
+    const int colc = min(max(col, 0), n1 - 1);
+    const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
+    const double* src = a.buf[parity] + o + colc;
+    double* dst = a.buf[parity ^ 1] + o + colc;
+    const double c1 = uniform(a.c1[s]), c2 = uniform(a.c2[s]);
+    const double gh1 = uniform(a.gh1[s]);
+    // column 0 receives half the corner source through its L2 = 0 face (the
+    // L1 sweep's row 0 the other half, through its L1 = 0 face)
+    const double ghost2 = col == 0 ? uniform(a.gh2[s]) : 0.0;
+    const double d1 = uniform(a.L1[s]) / n1, d2 = uniform(a.L2[s]) / n2;
+    const double L1c = (col + 0.5) * d1;
+
+    ColStage s1{0.0, 0.0, 0.0}, s2{0.0, 0.0, 0.0}, s3{0.0, 0.0, 0.0};
+    double u0_1 = 0.0, u0_2 = 0.0, u0_3 = 0.0;   // L2 stage inputs at rows R-1, R-2, R-3
+    double m00 = 0.0, m01 = 0.0, m02 = 0.0;     // this column's sums of f, L2 f, L2^2 f
+    double hL1 = 0.0, hL2 = 0.0;                 // stage-weighted outflow face values
+    // input rows R0..R1: the tile's rows plus the L2 halo; the output row is R - stages
+    const int R0 = r0 - 2 * H::stages, R1 = r1 + H::stages - 1;
+    // a ring keeps kColAhead row loads in flight; rows outside [0, n2) read a
+    // clamped in-range row whose value is not used
+    auto load_row = [&](int R) -> double { return src[(int64_t)min(max(R, 0), n2 - 1) * n1]; };
+    double ring[kColAhead];
+#pragma unroll
+    for (int j = 0; j < kColAhead; ++j) ring[j] = load_row(R0 + j);
+
+    // One input row R.  FAST: an interior tile and a row whose L2 stage rows
+    // all lie inside [0, n2): no exterior masks, ghost rows or outflow faces.
+    auto row = [&](auto fast, int R, double raw) {
+        constexpr bool FAST = decltype(fast)::value;
+        // L1 sweep of row R (rows outside the domain are the L2 ghost / zero)
+        double x;
+        if (!FAST && R < 0) {
+            x = ghost2;
+        } else if (!FAST && R >= n2) {
+            x = 0.0;
+        } else {
+            double hN;
+            if (FAST || interior) {
+                x = row_sweep_tile<SCHEME, false>(raw, c1, 0.0, false, false, &hN);
+            } else {
+                const double g1 = R == 0 ? gh1 : 0.0;   // row 0's inflow ghost
+                x = row_sweep_tile<SCHEME, true>(left_ext ? g1 : (right_ext ? 0.0 : raw), c1, g1, left_ext, right_ext,
+                                                 &hN);
+                if (col == n1 - 1 && R >= r0 && R < r1) hL1 += hN;
+            }
+        }
+        // L2 sweep: the stages pipelined down the column
+        double v, Fs[3];
+        int r;
+        if constexpr (RK) {
+            const double v1 = col_feed<SCHEME, !FAST>(s1, x, c2, 0.0, 0.0, 1.0, true, R - 1, n2, ghost2, &Fs[0]);
+            const double v2 = col_feed<SCHEME, !FAST>(s2, v1, c2, u0_2, 0.75, 0.25, false, R - 2, n2, ghost2, &Fs[1]);
+            v = col_feed<SCHEME, !FAST>(s3, v2, c2, u0_3, 1.0 / 3.0, 2.0 / 3.0, false, R - 3, n2, ghost2, &Fs[2]);
+            r = R - 3;
+            u0_3 = u0_2;
+            u0_2 = u0_1;
+            u0_1 = x;
+        } else {
+            v = col_feed<SCHEME, !FAST>(s1, x, c2, 0.0, 0.0, 1.0, true, R - 1, n2, ghost2, &Fs[0]);
+            r = R - 1;
+        }
+        // the face past L2_max of each stage is formed when that stage emits row
+        // n2 - 1, i.e. while rows n2 .. n2 + stages - 1 are fed (only in the tile
+        // that owns row n2 - 1)
+        if (!FAST && R >= n2 && r1 == n2) {
+            if constexpr (RK) {
+                hL2 += R == n2 ? Fs[0] * (1.0 / 6.0) : (R == n2 + 1 ? Fs[1] * (1.0 / 6.0) : Fs[2] * (2.0 / 3.0));
+            } else {
+                hL2 += Fs[0];
+            }
+        }
+        if (r >= r0 && r < r1) {
+            if (out_lane) dst[(int64_t)r * n1] = v;
+            const double f = out_lane ? v : 0.0;
+            const double L2c = (r + 0.5) * d2;
+            m00 += f;
+            m01 = fma(L2c, f, m01);
+            m02 = fma(L2c * L2c, f, m02);
+        }
+    };
+    for (int Rb = R0; Rb <= R1; Rb += kColAhead) {
+        if (interior && Rb >= H::stages && Rb + kColAhead - 1 <= min(R1, n2 - 1)) {
+#pragma unroll
+            for (int j = 0; j < kColAhead; ++j) {
+                const double raw = ring[j];
+                ring[j] = load_row(Rb + j + kColAhead);
+                row(std::true_type{}, Rb + j, raw);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kColAhead; ++j) {
+                const int R = Rb + j;
+                if (R > R1) break;
+                const double raw = ring[j];
+                ring[j] = load_row(R + kColAhead);
+                row(std::false_type{}, R, raw);
+            }
+        }
+    }
+    const double dA = d1 * d2;
+    const double m10 = wave_sum(L1c * m00) * dA;   // the column's L1 is constant
+    const double m12 = wave_sum(L1c * m02) * dA;
+    m00 = wave_sum(m00) * dA;
+    m01 = wave_sum(m01) * dA;
+    // number leaving through L1_max (rows of this tile) and L2_max (its columns):
+    // dt G1 hN d2 per row and dt G2 hN d1 per column, with dt G = c dL
+    const double outf = wave_sum(c1 * (out_lane ? hL1 : 0.0) + c2 * (out_lane ? hL2 : 0.0)) * dA;
+    if (lane == 0) {
+        double* p = a.part + (int64_t)b * 5;
+        p[0] = m00; p[1] = m10; p[2] = m01; p[3] = m12; p[4] = outf;
     }
 }
 
@@ -290,19 +358,16 @@ __global__ void k_out2d(Fvm2dArgs a, double* f_out) {
 
 }  // namespace
 
-hipError_t launch_rows2d(int cls, const Fvm2dArgs& a, int parity, int begin, int count, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    switch (cls) {
-        case 0: hipLaunchKernelGGL(k_rows2d<1>, dim3(count), dim3(64), 0, st, a, parity, begin); break;
-        case 1: hipLaunchKernelGGL(k_rows2d<9>, dim3(count), dim3(64), 0, st, a, parity, begin); break;
-        case 2: hipLaunchKernelGGL(k_rows2d<17>, dim3(count), dim3(64), 0, st, a, parity, begin); break;
-        default: hipLaunchKernelGGL(k_rows2d<25>, dim3(count), dim3(64), 0, st, a, parity, begin); break;
-    }
-    return hipGetLastError();
+int step2d_tile_width(int scheme) {
+    return scheme == PBE_SCHEME_LW_TVD ? Halo2d<PBE_SCHEME_LW_TVD>::width : Halo2d<PBE_SCHEME_SSPRK3>::width;
 }
 
-hipError_t launch_cols2d(const Fvm2dArgs& a, int parity, hipStream_t st) {
-    hipLaunchKernelGGL(k_cols2d, dim3(a.n_cb), dim3(64), 0, st, a, parity);
+hipError_t launch_step2d(const Fvm2dArgs& a, int parity, hipStream_t st) {
+    const int blocks = (a.n_cb + 7) / 8 * 8;   // a multiple of 8 (see tile_of_block)
+    if (a.scheme == PBE_SCHEME_LW_TVD)
+        hipLaunchKernelGGL(k_step2d<PBE_SCHEME_LW_TVD>, dim3(blocks), dim3(64), 0, st, a, parity);
+    else
+        hipLaunchKernelGGL(k_step2d<PBE_SCHEME_SSPRK3>, dim3(blocks), dim3(64), 0, st, a, parity);
     return hipGetLastError();
 }
 

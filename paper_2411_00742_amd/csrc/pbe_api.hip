@@ -95,7 +95,6 @@ struct pbe_handle {
     // 2D
     bool two_d = false;
     Fvm2dArgs a2{};
-    int row_begin[kRowClasses] = {}, row_count[kRowClasses] = {};
     int64_t g2 = 0;                  // global step of the 2D solve (parity selects the buffer)
     std::vector<int32_t> n1v, n2v;   // 2D grid sizes (host copy, for rebuilding the column blocks)
     int32_t* d_cb[3] = {};           // 2D column-block tables (sim, col0, row0), sized for the shortest segment
@@ -113,6 +112,7 @@ struct pbe_handle {
 namespace {
 
 int validate2d(const pbe_problem* p);
+constexpr int k2dMaxCells = 1 << 16;   // cells along either axis of a 2D grid
 
 // closure blob: finite, positive input scales, a non-empty box, s_min >= 0;
 // the closure kernels run SSP-RK3 on grids of up to 1024 cells
@@ -205,13 +205,12 @@ int validate_common(const pbe_problem* p) {
 int validate2d(const pbe_problem* p) {
     int rc = validate_common(p);
     if (rc != PBE_OK) return rc;
-    // the split solver runs SSP-RK3 sweeps, forward only, outputs are moments and final states
-    if (p->scheme != PBE_SCHEME_SSPRK3 || p->ckpt_every != 0 || (p->flags & (PBE_FLAG_RECORD_F | PBE_FLAG_RECORD_RATES)))
-        return PBE_EUNSUPPORTED;
+    // the split solver is forward only; its outputs are moments and final states
+    if (p->ckpt_every != 0 || (p->flags & (PBE_FLAG_RECORD_F | PBE_FLAG_RECORD_RATES))) return PBE_EUNSUPPORTED;
     int64_t total = 0;
     for (int s = 0; s < p->n_sims; ++s) {
         const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
-        if (n1 < 4 || n1 > kWave * kMaxCellsPerLane || n2 < 4 || n2 > 8192) return PBE_EINVAL;
+        if (n1 < 4 || n1 > k2dMaxCells || n2 < 4 || n2 > k2dMaxCells) return PBE_EINVAL;
         if (!is_finite(p->L_max[2 * s]) || !(p->L_max[2 * s] > 0.0) || !is_finite(p->L_max[2 * s + 1]) ||
             !(p->L_max[2 * s + 1] > 0.0))
             return PBE_EINVAL;
@@ -368,8 +367,8 @@ int write_outputs(pbe_handle* h, double* f_out, double* mom_out, double* C_out, 
 }
 
 // ----------------------------------------------------------------- 2D
-constexpr int k2dSeg = 128;         // rows per L2-sweep block (default; pbe_tune may change it)
-constexpr int k2dSegMin = 64;       // shortest segment the column-block tables are sized for
+constexpr int k2dSeg = 64;          // rows per 2D tile (default; pbe_tune may change it)
+constexpr int k2dSegMin = 32;       // shortest segment the tile tables are sized for
 constexpr int k2dStepsPerGraph = 50;  // global steps captured per graph launch (even)
 
 double step_bound2d(const pbe_problem* p, int s) {
@@ -396,13 +395,15 @@ double step_bound2d(const pbe_problem* p, int s) {
     return p->t_end / dt_min + p->n_samples + 2.0;
 }
 
-// L2-sweep work list for a segment length: blocks of 64 columns x seg rows, sim by sim
+// 2D work list for a segment length: tiles of step2d_tile_width columns x seg
+// rows, sim by sim, row segments of one column strip consecutive
 int set_col_blocks(pbe_handle* h, int seg) {
     const int S = h->S;
+    const int tw = step2d_tile_width(h->p.scheme);
     std::vector<int32_t> cb[3], first(S + 1, 0);
     for (int s = 0; s < S; ++s) {
         first[s] = (int)cb[0].size();
-        for (int c0 = 0; c0 < h->n1v[s]; c0 += kWave)
+        for (int c0 = 0; c0 < h->n1v[s]; c0 += tw)
             for (int r0 = 0; r0 < h->n2v[s]; r0 += seg) {
                 cb[0].push_back(s);
                 cb[1].push_back(c0);
@@ -439,20 +440,6 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
     for (int s = 0; s < S; ++s) cap = std::max(cap, step_bound2d(p, s));
     const int step_cap = p->max_steps > 0 ? p->max_steps : (int)std::min(1.0e9, std::ceil(cap * 1.05) + 8.0);
 
-    // work lists: rows grouped by class of cells per lane; column blocks sim by sim
-    std::vector<int32_t> row_sim, row_j;
-    for (int c = 0; c < kRowClasses; ++c) {
-        h->row_begin[c] = (int)row_sim.size();
-        for (int s = 0; s < S; ++s) {
-            const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
-            if (rows2d_class_of(n1) != c) continue;
-            for (int j = 0; j < n2; ++j) {
-                row_sim.push_back(s);
-                row_j.push_back(j);
-            }
-        }
-        h->row_count[c] = (int)row_sim.size() - h->row_begin[c];
-    }
     std::vector<int32_t> n1v(S), n2v(S);
     std::vector<double> L1v(S), L2v(S);
     for (int s = 0; s < S; ++s) {
@@ -464,7 +451,7 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
 
     Alloc& m = h->mem;
     Fvm2dArgs& a = h->a2;
-    a.n_sims = S; a.n_samples = ns; a.law = p->law; a.sol_law = p->sol_law;
+    a.n_sims = S; a.n_samples = ns; a.law = p->law; a.sol_law = p->sol_law; a.scheme = p->scheme;
     a.cs0 = p->cs0; a.cs1 = p->cs1; a.alpha = p->alpha; a.cfl = p->cfl; a.dt_max = p->dt_max; a.t_end = p->t_end;
     double* d_ts = m.get<double>(ns);
     int64_t* d_off = m.get<int64_t>(S + 1);
@@ -477,26 +464,25 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
     double* d_f0 = m.cells(h->total);
     a.buf[0] = m.cells(h->total);
     a.buf[1] = m.cells(h->total);
-    a.C = m.get<double>(S); a.t = m.get<double>(S); a.mu12 = m.get<double>(S);
+    a.C = m.get<double>(S); a.t = m.get<double>(S); a.mu12 = m.get<double>(S); a.outflow = m.get<double>(S);
     a.step = m.get<int32_t>(S); a.next = m.get<int32_t>(S); a.status = m.get<int32_t>(S);
     a.active = m.get<int32_t>(S); a.n_active = m.get<int32_t>(1);
     a.c1 = m.get<double>(S); a.c2 = m.get<double>(S); a.gh1 = m.get<double>(S); a.gh2 = m.get<double>(S);
     a.dt = m.get<double>(S); a.hit = m.get<int32_t>(S);
-    int32_t* d_row_sim = m.get<int32_t>(row_sim.size());
-    int32_t* d_row_j = m.get<int32_t>(row_j.size());
-    int64_t max_cb = 0;   // column blocks at the shortest segment
+    int64_t max_cb = 0;   // tiles at the shortest segment
+    const int tw = step2d_tile_width(p->scheme);
     for (int s = 0; s < S; ++s)
-        max_cb += (int64_t)((n1v[s] + kWave - 1) / kWave) * ((n2v[s] + k2dSegMin - 1) / k2dSegMin);
+        max_cb += (int64_t)((n1v[s] + tw - 1) / tw) * ((n2v[s] + k2dSegMin - 1) / k2dSegMin);
+    if (max_cb > (int64_t)std::numeric_limits<int32_t>::max() / 2) return PBE_EINVAL;
     for (int k = 0; k < 3; ++k) h->d_cb[k] = m.get<int32_t>(max_cb);
     h->d_cb_first = m.get<int32_t>(S + 1);
-    a.part = m.get<double>(max_cb * 4);
+    a.part = m.get<double>(max_cb * 5);
     a.mom_s = m.get<double>((size_t)S * ns * 4);
     a.C_s = m.get<double>((size_t)S * ns);
     a.samp_step = m.get<int32_t>((size_t)S * ns);
     if (!m.ok) return PBE_ENOMEM;
     a.t_samples = d_ts; a.off = d_off; a.n1 = d_n1; a.n2 = d_n2; a.L1 = d_L1; a.L2 = d_L2; a.par = d_par;
     a.C0 = d_C0; a.f0 = d_f0;
-    a.row_sim = d_row_sim; a.row_j = d_row_j;
     a.step_cap = step_cap;
     h->n1v = n1v;
     h->n2v = n2v;
@@ -514,9 +500,7 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
         hipMemcpy(d_L2, L2v.data(), sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_par, p->par, sizeof(double) * S * PBE_NPAR, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_C0, p->C0, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_row_sim, row_sim.data(), sizeof(int32_t) * row_sim.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_row_j, row_j.data(), sizeof(int32_t) * row_j.size(), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess)
         return PBE_EDEVICE;
     h->active_host.assign(S, 0);
     return set_col_blocks(h, k2dSeg);
@@ -525,9 +509,7 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
 // one global step of every active 2D sim
 int step2d_once(pbe_handle* h) {
     const int parity = (int)(h->g2 & 1);
-    for (int c = 0; c < kRowClasses; ++c)
-        HIP_OK(launch_rows2d(c, h->a2, parity, h->row_begin[c], h->row_count[c], h->stream));
-    HIP_OK(launch_cols2d(h->a2, parity, h->stream));
+    HIP_OK(launch_step2d(h->a2, parity, h->stream));
     HIP_OK(launch_final2d(h->a2, 0, h->stream));
     ++h->g2;
     return PBE_OK;
@@ -704,7 +686,7 @@ int tune_handle(pbe_handle* h, int trial_steps, bool use_cache, pbe_tuning* out)
     }
     std::vector<pbe_tuning> cands;
     if (h->two_d) {
-        for (int seg : {k2dSeg, 64, 256, 512}) {
+        for (int seg : {k2dSeg, 32, 128, 256}) {
             pbe_tuning t{};
             t.seg_2d = seg;
             cands.push_back(t);

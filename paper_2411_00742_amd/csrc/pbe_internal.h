@@ -94,11 +94,11 @@ struct Adj1dArgs {
 // dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2
 constexpr int kClosureTape = 13;
 
-// 2D Godunov-split solver: per global step an L1 row sweep (in place), an L2
-// column march (double buffered) with moment partials, and a per-sim finalize.
+// 2D Godunov-split solver: per global step one pass over tiles that sweeps
+// L1 and then L2 (double buffered) with moment partials, and a per-sim finalize.
 struct Fvm2dArgs {
     int32_t n_sims, n_samples;
-    int32_t law, sol_law;
+    int32_t law, sol_law, scheme, pad0_;
     double cs0, cs1, alpha, cfl, dt_max, t_end;
     const double* t_samples;
     const int64_t* off;        // [S+1] cell offsets (sim s stored [n2][n1])
@@ -114,6 +114,7 @@ struct Fvm2dArgs {
     double* C;                 // [S]
     double* t;                 // [S]
     double* mu12;              // [S] volume moment of the current state
+    double* outflow;           // [S] number that left through L1_max and L2_max
     int32_t* step;             // [S]
     int32_t* next;             // [S]
     int32_t* status;           // [S]
@@ -125,16 +126,13 @@ struct Fvm2dArgs {
     double* gh2;
     double* dt;                // [S]
     int32_t* hit;              // [S] step lands on the next sample time
-    // L1 sweep: row tasks grouped by class of cells per lane
-    const int32_t* row_sim;    // [n_rows]
-    const int32_t* row_j;      // [n_rows]
-    // L2 sweep: column blocks (64 columns x seg rows)
+    // tiles (step2d_tile_width(scheme) columns x seg rows), sim by sim
     const int32_t* cb_sim;     // [n_cb]
     const int32_t* cb_col0;
     const int32_t* cb_row0;
-    const int32_t* cb_first;   // [S+1] first column block of each sim
+    const int32_t* cb_first;   // [S+1] first tile of each sim
     int32_t n_cb, seg;
-    double* part;              // [n_cb][4] partial moments of the swept state
+    double* part;              // [n_cb][5] moments mu_00, mu_10, mu_01, mu_12 of the new state and outflow
     double* mom_s;             // [S][n_samples][4]: mu_00, mu_10, mu_01, mu_12
     double* C_s;               // [S][n_samples]
     int32_t* samp_step;        // [S][n_samples]
@@ -152,9 +150,6 @@ inline int fvm1d_class_of(int n_cells) {
     const int K = (n_cells + 63) / 64;
     return K < kSolveKlo[1] ? 0 : K < kSolveKlo[2] ? 1 : K < kSolveKlo[3] ? 2 : 3;
 }
-// 2D row sweeps: classes of eight cells per lane (1-8, ..., 25-32)
-constexpr int kRowClasses = 4;
-inline int rows2d_class_of(int n_cells) { return ((n_cells + 63) / 64 - 1) / 8; }
 // 1D solves: one wavefront per simulation in the four classes above, or
 // (pairs) grids of more than 1024 cells on a wave pair with K = ceil(N/128) =
 // 9..16 in class 2 and class 3 empty.  Classes 0 and 1 are the same either way.
@@ -169,8 +164,8 @@ constexpr int kAdjClasses = 2;   // adjoint classes: cells per lane 1-8, 9-16 (g
 hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
 int adj1d_class_resident_blocks(int cls, int closure);
-hipError_t launch_rows2d(int cls, const Fvm2dArgs& a, int parity, int begin, int count, hipStream_t st);
-hipError_t launch_cols2d(const Fvm2dArgs& a, int parity, hipStream_t st);
+int step2d_tile_width(int scheme);   // output columns of one 2D tile
+hipError_t launch_step2d(const Fvm2dArgs& a, int parity, hipStream_t st);
 hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st);
 hipError_t launch_out2d(const Fvm2dArgs& a, double* f_out, hipStream_t st);
 // learned closure (closure.hip)

@@ -95,3 +95,29 @@ def test_full_shape_workload_invariants(torch_cuda, oracle):
         assert fs[s].min() >= -1e-12 * fs[s].max()
     small = int(np.argmin(p.n_cells[:, 0]))
     compare(p, g, [small], oracle)
+
+
+@pytest.mark.parametrize("scheme,nu", [(W.SCHEME_SSPRK3, 0.5), (W.SCHEME_LW_TVD, 0.9)])
+def test_tile_edges_and_both_schemes(torch_cuda, oracle, scheme, nu):
+    """Grids whose widths straddle the 2D tile width (55 columns for SSP-RK3, 61 for the one-step
+    scheme) and whose heights straddle the row segment, plus rows wider than 2048 cells."""
+    shapes = [(54, 20), (55, 129), (56, 127), (61, 128), (62, 130), (110, 64), (111, 65), (3000, 24), (4, 4)]
+    p = problem2d(shapes, t_end=150.0).with_(scheme=scheme, cfl=nu)
+    g = run_gpu(p)
+    compare(p, g, range(len(shapes)), oracle)
+
+
+def test_outflow_through_both_far_edges(torch_cuda, oracle):
+    """Seeds near L1_max and L2_max with fast growth: crystals leave through both outer edges; the
+    status bit agrees with the oracle and everything else still matches."""
+    shapes = [(80, 60), (130, 70)]
+    p = problem2d(shapes, t_end=400.0, S_boost=1.3)
+    seeds = [W.gaussian_seed_2d(n1, n2, 1200.0, 600.0, (1100.0, 540.0), (40.0, 30.0), 0.2, 1e9).ravel()
+             for (n1, n2) in shapes]
+    p = p.with_(f0=np.concatenate(seeds), dt_max=5.0)
+    g = run_gpu(p)
+    for i in range(p.n_sims):
+        r = oracle.solve2d(p, i)
+        assert r["status"] & 2, r["status"]
+        assert int(g["status"][i]) == r["status"], (i, g["status"][i], r["status"])
+    compare(p, g, range(p.n_sims), oracle)
