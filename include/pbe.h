@@ -60,8 +60,11 @@ enum { PBE_FLAG_DEVICE_PTRS = 1,  /* output/cotangent pointers are device memory
        PBE_FLAG_RECORD_RATES = 8 };  /* 1D: record (dt, G0, B) of every step, read with pbe_rate_log */
 
 /* per-sim parameter row */
+/* kg [m/s], g, kb [#/(m^3 s)], b, gamma [1/um], kg2, g2 (2D second axis), Eg, Eb [K] (Arrhenius
+ * law), T0, T1 [degC], t_ramp [s], Eg2 [K] (2D second axis, Arrhenius law: App. A Eq. (A.2) takes
+ * one activation temperature per axis) */
 enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G2, PBE_P_EG, PBE_P_EB,
-       PBE_P_T0, PBE_P_T1, PBE_P_TRAMP, PBE_NPAR };
+       PBE_P_T0, PBE_P_T1, PBE_P_TRAMP, PBE_P_EG2, PBE_NPAR };
 #define PBE_NGRAD 5   /* pbe_grad returns d/d(kg, g, kb, b, gamma) per sim */
 
 /* Learned closure (law PBE_LAW_MLP): the empirical hybrid model of Sec. 4.2,

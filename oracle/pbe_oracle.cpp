@@ -104,12 +104,13 @@ template <int ND> Dual<ND> power(const Dual<ND>& x, const Dual<ND>& p) {
 // ---------------------------------------------------------------------------
 // Process and kinetics.
 // ---------------------------------------------------------------------------
-enum { K_KG, K_G, K_KB, K_B, K_GAMMA, K_KG2, K_G2, K_EG, K_EB, K_T0, K_T1, K_TRAMP };
+enum { K_KG, K_G, K_KB, K_B, K_GAMMA, K_KG2, K_G2, K_EG, K_EB, K_T0, K_T1, K_TRAMP, K_EG2 };
 
 template <class R>
 struct Kinetics {
     R kg, g, kb, b, gamma, kg2, g2;
-    double Eg, Eb;
+    double Eg, Eb, Eg2;
+    std::vector<R> poly;   // a_1..a_k of the polynomial growth law
 };
 
 template <class R>
@@ -117,7 +118,22 @@ Kinetics<R> load_kinetics(const double* par) {
     Kinetics<R> k;
     k.kg = R(par[K_KG]); k.g = R(par[K_G]); k.kb = R(par[K_KB]); k.b = R(par[K_B]);
     k.gamma = R(par[K_GAMMA]); k.kg2 = R(par[K_KG2]); k.g2 = R(par[K_G2]);
-    k.Eg = par[K_EG]; k.Eb = par[K_EB];
+    k.Eg = par[K_EG]; k.Eb = par[K_EB]; k.Eg2 = par[K_EG2];
+    return k;
+}
+
+// The kinetics of one 1D simulation: its parameter row and, for the polynomial
+// law, its coefficients (tangent direction: coefficient j moves along v[j]).
+template <class R>
+Kinetics<R> load_kinetics_sim(const ref_sim1d* s, const double* v = nullptr, int dir = -1) {
+    Kinetics<R> k = load_kinetics<R>(s->par);
+    if (s->poly && s->n_poly > 0) {
+        k.poly.resize(s->n_poly);
+        for (int j = 0; j < s->n_poly; ++j) {
+            k.poly[j] = R(s->poly[j]);
+            if (v && dir >= 0) set_tangent(k.poly[j], dir, v[j]);
+        }
+    }
     return k;
 }
 
@@ -159,8 +175,18 @@ void rate_laws(int law, const Kinetics<R>& k, const Q& T, R Sp, R& G0, R& G2, R&
     B = k.kb * power(Sp, k.b);
     if (law == REF_LAW_ARRHENIUS) {
         G0 = G0 * exp(-k.Eg / (T + 273.15));
-        G2 = G2 * exp(-k.Eg / (T + 273.15));
+        G2 = G2 * exp(-k.Eg2 / (T + 273.15));
         B = B * exp(-k.Eb / (T + 273.15));
+    }
+    if (law == REF_LAW_POLY) {
+        // Eq. (poly_growth_rate): sum of a_j S^j over j = 1..k
+        G0 = R(0.0);
+        R Sj = Sp;
+        for (size_t j = 0; j < k.poly.size(); ++j) {
+            G0 = G0 + k.poly[j] * Sj;
+            Sj = Sj * Sp;
+        }
+        G2 = R(0.0);
     }
 }
 
@@ -732,9 +758,10 @@ int ref_solve1d(const ref_process* p, ref_sim1d* s) {
     if (p->law == REF_LAW_MLP) {
         if (!p->mlp) return -1;
         const Net<double> net = load_net<double>(p->mlp, p->mlp_precision, nullptr, -1);
-        return solve1d_impl<double>(p, s, load_kinetics<double>(s->par), nullptr, &net);
+        return solve1d_impl<double>(p, s, load_kinetics_sim<double>(s), nullptr, &net);
     }
-    return solve1d_impl<double>(p, s, load_kinetics<double>(s->par), nullptr);
+    if (p->law == REF_LAW_POLY && (!s->poly || s->n_poly < 1)) return -1;
+    return solve1d_impl<double>(p, s, load_kinetics_sim<double>(s), nullptr);
 }
 
 int ref_solve1d_batch(const ref_process* p, ref_sim1d* sims, int32_t n_sims, int32_t n_threads) {
@@ -753,7 +780,7 @@ static std::vector<double> primal_schedule(const ref_process* p, const ref_sim1d
     s0.dt_log = dts.data();
     s0.steps = &steps;
     s0.max_steps = cap;
-    solve1d_impl<double>(p, &s0, load_kinetics<double>(s0.par), nullptr, net);
+    solve1d_impl<double>(p, &s0, load_kinetics_sim<double>(&s0), nullptr, net);
     dts.resize(steps);
     return dts;
 }
@@ -762,7 +789,7 @@ int ref_tangent1d(const ref_process* p, ref_sim1d* s, int32_t dt_mode, double* d
     typedef Dual<REF_NTAN> D;
     if (!p || !s || s->n < 1 || p->law == REF_LAW_MLP) return -1;
     if (dt_mode != REF_DT_DIFF && dt_mode != REF_DT_FROZEN) return -1;
-    Kinetics<D> k = load_kinetics<D>(s->par);
+    Kinetics<D> k = load_kinetics_sim<D>(s);
     k.kg.d[0] = 1.0; k.g.d[1] = 1.0; k.kb.d[2] = 1.0; k.b.d[3] = 1.0; k.gamma.d[4] = 1.0;
     std::vector<D> tf((size_t)s->n_samples * s->n), tm((size_t)s->n_samples * 4), tc(s->n_samples);
     Tangents<D> tan;
@@ -901,9 +928,41 @@ int ref_tangent1d_mlp(const ref_process* p, ref_sim1d* s, int32_t dt_mode, const
     return 0;
 }
 
+int ref_tangent1d_poly(const ref_process* p, ref_sim1d* s, int32_t dt_mode, const double* v, double* dF, double* dM,
+                       double* dC) {
+    typedef Dual<2> D;
+    if (!p || !s || s->n < 1 || p->law != REF_LAW_POLY || !s->poly || s->n_poly < 1 || !v) return -1;
+    if (dt_mode != REF_DT_DIFF && dt_mode != REF_DT_FROZEN) return -1;
+    Kinetics<D> k = load_kinetics_sim<D>(s, v, 0);
+    k.gamma.d[1] = 1.0;
+    std::vector<D> tf((size_t)s->n_samples * s->n), tm((size_t)s->n_samples * 4), tc(s->n_samples);
+    Tangents<D> tan;
+    tan.f_samples = dF ? &tf : nullptr;
+    tan.mom = &tm;
+    tan.C = &tc;
+    ref_sim1d s1 = *s;
+    std::vector<double> dts;
+    if (dt_mode == REF_DT_FROZEN) {
+        dts = primal_schedule(p, s, nullptr);
+        s1.dt_replay = dts.data();
+        s1.n_replay = (int)dts.size();
+        s1.max_steps = (int)dts.size();
+    }
+    solve1d_impl<D>(p, &s1, k, &tan);
+    for (int q = 0; q < s->n_samples; ++q)
+        for (int d = 0; d < 2; ++d) {
+            if (dC) dC[q * 2 + d] = tc[q].d[d];
+            for (int m = 0; m < 4; ++m)
+                if (dM) dM[(q * 4 + m) * 2 + d] = tm[q * 4 + m].d[d];
+            if (dF)
+                for (int i = 0; i < s->n; ++i) dF[((size_t)q * s->n + i) * 2 + d] = tf[(size_t)q * s->n + i].d[d];
+        }
+    return 0;
+}
+
 int ref_solve2d(const ref_process* p, ref_sim2d* s) {
     if (!p || !s || s->n1 < 1 || s->n2 < 1 || !s->f0 || !s->par) return -1;
-    if (p->law == REF_LAW_MLP) return -2;
+    if (p->law == REF_LAW_MLP || p->law == REF_LAW_POLY) return -2;
     return solve2d_impl(p, s);
 }
 
@@ -913,6 +972,7 @@ int ref_solve2d_batch(const ref_process* p, ref_sim2d* sims, int32_t n_sims, int
 
 int ref_mom1d(const ref_process* p, const double* par, double C0, const double* mu_init, int32_t n_samples,
               const double* t_samples, double rtol, double atol, double* mu_out, double* C_out) {
+    if (p->law == REF_LAW_MLP || p->law == REF_LAW_POLY) return -2;
     MomSystem sys{p, par, 1};
     double y[5] = {mu_init[0], mu_init[1], mu_init[2], mu_init[3], C0};
     std::vector<double> yo((size_t)n_samples * 5);

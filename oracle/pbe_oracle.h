@@ -28,7 +28,8 @@
  *
  * Per-simulation parameter row (REF_NPAR doubles):
  *   0 kg, 1 g, 2 kb, 3 b, 4 gamma [1/um], 5 kg2, 6 g2, 7 Eg [K], 8 Eb [K],
- *   9 T0, 10 T1, 11 t_ramp.
+ *   9 T0, 10 T1, 11 t_ramp, 12 Eg2 [K] (the second axis' growth activation
+ *   temperature of the Arrhenius law; App. A Eq. (A.2) has one per axis).
  */
 #ifndef PBE_ORACLE_H
 #define PBE_ORACLE_H
@@ -39,11 +40,14 @@
 extern "C" {
 #endif
 
-#define REF_NPAR 12
+#define REF_NPAR 13
 #define REF_NTAN 5          /* tangent directions: kg, g, kb, b, gamma */
 
 enum { REF_SCHEME_SSPRK3 = 0, REF_SCHEME_LW_TVD = 1 };
-enum { REF_LAW_POWER = 0, REF_LAW_ARRHENIUS = 1, REF_LAW_MLP = 2 };
+/* REF_LAW_POLY: growth G0 = a_1 S + a_2 S^2 + ... + a_k S^k with S = C/Csat - 1 > 0 (the
+ * polynomial growth law of Sec. 4.1, Eq. (poly_growth_rate), in um per time unit; the sim's
+ * poly[] holds a_1..a_k), nucleation by the power law kb S^b. */
+enum { REF_LAW_POWER = 0, REF_LAW_ARRHENIUS = 1, REF_LAW_MLP = 2, REF_LAW_POLY = 3 };
 enum { REF_SOL_LINEAR = 0, REF_SOL_EXP = 1 };
 enum { REF_SIM_OK = 0, REF_SIM_NONFINITE = 1, REF_SIM_OUTFLOW = 2, REF_SIM_FALLBACK = 4 };
 
@@ -91,6 +95,8 @@ typedef struct {
     const double *t_samples;  /* [n_samples] ascending in (0, t_end] */
     const double *dt_replay;
     const double *G0_replay, *B_replay;
+    int32_t n_poly;           /* law == REF_LAW_POLY: number of coefficients k */
+    const double *poly;       /* law == REF_LAW_POLY: [n_poly] a_1..a_k */
     /* outputs */
     double *f_samples;        /* [n_samples][n] */
     double *mom;              /* [n_samples][4]  mu_0..mu_3 */
@@ -150,6 +156,11 @@ int ref_mlp_vjp(const float *blob, int32_t precision, int32_t n, const double *z
  * dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
 int ref_tangent1d_mlp(const ref_process *p, ref_sim1d *s, int32_t dt_mode, const double *v, double *dF, double *dM,
                       double *dC);
+/* Polynomial growth law: forward-mode derivatives along the coefficient
+ * direction v[n_poly] (tangent 0) and along gamma (tangent 1), steps as
+ * dt_mode says.  dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
+int ref_tangent1d_poly(const ref_process *p, ref_sim1d *s, int32_t dt_mode, const double *v, double *dF, double *dM,
+                       double *dC);
 
 int ref_solve2d(const ref_process *p, ref_sim2d *s);
 int ref_solve2d_batch(const ref_process *p, ref_sim2d *sims, int32_t n_sims, int32_t n_threads);

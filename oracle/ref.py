@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpbe_oracle.so")
 SOURCES = [os.path.join(HERE, "pbe_oracle.cpp")]
-NPAR = 12
+NPAR = 13
 NTAN = 5
 DT_DIFF, DT_FROZEN = 0, 1
 MLP_NC = 18
@@ -49,7 +49,7 @@ class Sim1D(C.Structure):
                 ("n_rates_replay", C.c_int32),
                 ("L_max", C.c_double), ("C0", C.c_double),
                 ("f0", _dp), ("par", _dp), ("t_samples", _dp), ("dt_replay", _dp),
-                ("G0_replay", _dp), ("B_replay", _dp),
+                ("G0_replay", _dp), ("B_replay", _dp), ("n_poly", C.c_int32), ("poly", _dp),
                 ("f_samples", _dp), ("mom", _dp), ("C", _dp), ("f_final", _dp), ("dt_log", _dp),
                 ("G0_log", _dp), ("B_log", _dp),
                 ("steps", _ip), ("status", _ip),
@@ -93,6 +93,7 @@ def lib():
         L.ref_mlp_forward.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
         L.ref_mlp_vjp.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
         L.ref_tangent1d_mlp.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp, _dp]
+        L.ref_tangent1d_poly.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -146,6 +147,8 @@ class _Sim1DBuffers:
             self.G0r = np.ascontiguousarray(rates_replay[0], dtype=np.float64)
             self.Br = np.ascontiguousarray(rates_replay[1], dtype=np.float64)
             assert self.G0r.shape == self.Br.shape
+        poly = getattr(prob, "poly", None)
+        self.poly = None if poly is None else np.ascontiguousarray(poly[s], dtype=np.float64)
         self.f_samples = np.zeros((ns, n)) if record_f else None
         self.mom = np.zeros((ns, 4))
         self.C = np.zeros(ns)
@@ -168,6 +171,7 @@ class _Sim1DBuffers:
                             L_max=float(prob.L_max[s]), C0=float(prob.C0[s]),
                             f0=_ptr(self.f0), par=_ptr(self.par), t_samples=_ptr(self.ts),
                             dt_replay=_ptr(self.replay), G0_replay=_ptr(self.G0r), B_replay=_ptr(self.Br),
+                            n_poly=0 if self.poly is None else len(self.poly), poly=_ptr(self.poly),
                             f_samples=_ptr(self.f_samples), mom=_ptr(self.mom),
                             C=_ptr(self.C), f_final=_ptr(self.f_final), dt_log=_ptr(self.dt_log),
                             G0_log=_ptr(self.G0_log), B_log=_ptr(self.B_log),
@@ -368,3 +372,24 @@ def tangent1d_mlp(prob, s: int, v, with_f: bool = True, max_steps: int | None = 
 
 def bf16(x: float) -> float:
     return lib().ref_bf16(float(x))
+
+
+def tangent1d_poly(prob, s: int, v, with_f: bool = True, max_steps: int | None = None, frozen_dt: bool = False):
+    """Polynomial growth law: derivatives along the coefficient direction v (tangent 0) and gamma
+    (tangent 1).  Returns dict with dF [ns, n, 2] (if with_f), dM [ns, 4, 2], dC [ns, 2]."""
+    buf = _Sim1DBuffers(prob, s, False, max_steps, None, 0)
+    n, ns = int(prob.n_cells[s]), len(prob.t_samples)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert buf.poly is not None and v.shape == buf.poly.shape
+    dF = np.zeros((ns, n, 2)) if with_f else None
+    dM = np.zeros((ns, 4, 2))
+    dC = np.zeros((ns, 2))
+    p = process_of(prob)
+    rc = lib().ref_tangent1d_poly(C.byref(p), C.byref(buf.struct), DT_FROZEN if frozen_dt else DT_DIFF, _ptr(v),
+                                  _ptr(dF), _ptr(dM), _ptr(dC))
+    if rc != 0:
+        raise RuntimeError(f"ref_tangent1d_poly failed ({rc})")
+    out = dict(dM=dM, dC=dC)
+    if with_f:
+        out["dF"] = dF
+    return out

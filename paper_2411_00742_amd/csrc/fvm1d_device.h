@@ -179,21 +179,22 @@ __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& 
 struct Rates2 {
     double G1, G2, B, S;
 };
-__device__ __forceinline__ Rates2 rates_2d(const Process& p, const SimParams& q, double kg2, double g2, double C,
-                                           double t) {
+__device__ __forceinline__ Rates2 rates_2d(const Process& p, const SimParams& q, double kg2, double g2, double Eg2,
+                                           double C, double t) {
     Rates2 r;
     const double T = temperature(q, t);
     r.S = C / solubility(p, T) - 1.0;
     r.G1 = 0.0; r.G2 = 0.0; r.B = 0.0;
     if (r.S > 0.0) {
         const double lnS = log64(r.S);
-        double aG = 1.0, aB = 1.0;
+        double aG = 1.0, aG2 = 1.0, aB = 1.0;
         if (p.law == PBE_LAW_ARRHENIUS) {
             aG = exp64(-q.Eg / (T + 273.15));
+            aG2 = exp64(-Eg2 / (T + 273.15));
             aB = exp64(-q.Eb / (T + 273.15));
         }
         r.G1 = 1e6 * q.kg * exp64(q.g * lnS) * aG;
-        r.G2 = 1e6 * kg2 * exp64(g2 * lnS) * aG;
+        r.G2 = 1e6 * kg2 * exp64(g2 * lnS) * aG2;
         r.B = q.kb * exp64(q.b * lnS) * aB;
     }
     r.G1 = uniform(r.G1);

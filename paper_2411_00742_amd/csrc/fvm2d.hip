@@ -120,7 +120,7 @@ __device__ void finalize_sim(const Fvm2dArgs& a, int s, int init) {
     const Process p{a.law, a.scheme, a.sol_law, a.cs0, a.cs1, a.alpha, a.cfl, a.dt_max, a.t_end};
     const double* P = a.par + (size_t)s * PBE_NPAR;
     const SimParams q = load_params(P);
-    const double kg2 = uniform(P[PBE_P_KG2]), g2 = uniform(P[PBE_P_G2]);
+    const double kg2 = uniform(P[PBE_P_KG2]), g2 = uniform(P[PBE_P_G2]), Eg2 = uniform(P[PBE_P_EG2]);
     const int n1 = uniform(a.n1[s]), n2 = uniform(a.n2[s]);
     const double d1 = uniform(a.L1[s]) / n1, d2 = uniform(a.L2[s]) / n2;
     const int ns = a.n_samples;
@@ -190,7 +190,7 @@ __device__ void finalize_sim(const Fvm2dArgs& a, int s, int init) {
         status |= PBE_SIM_STEPCAP;
         active = 0;
     } else {
-        const Rates2 r = rates_2d(p, q, kg2, g2, C, t);
+        const Rates2 r = rates_2d(p, q, kg2, g2, Eg2, C, t);
         const double t_next = uniform(next < ns ? a.t_samples[min(next, ns - 1)] : p.t_end);
         double lim = __builtin_huge_val();
         if (r.G1 > 0.0) lim = fmin(lim, d1 / r.G1);

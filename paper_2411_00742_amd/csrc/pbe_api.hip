@@ -221,7 +221,8 @@ int validate2d(const pbe_problem* p) {
         if (q[PBE_P_KG] < 0.0 || q[PBE_P_KG2] < 0.0 || q[PBE_P_KB] < 0.0 || !(q[PBE_P_G] > 0.0) ||
             !(q[PBE_P_G2] > 0.0) || !(q[PBE_P_B] > 0.0) || q[PBE_P_TRAMP] < 0.0)
             return PBE_EINVAL;
-        if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0)) return PBE_EINVAL;
+        if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0 || q[PBE_P_EG2] < 0.0))
+            return PBE_EINVAL;
         if (!(solubility(p, q[PBE_P_T0]) > 0.0) || !(solubility(p, q[PBE_P_T1]) > 0.0)) return PBE_EINVAL;
         total += (int64_t)n1 * n2;
     }

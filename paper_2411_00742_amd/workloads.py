@@ -33,12 +33,13 @@ SCHEME_LW_TVD = 1      # the paper's one-step limited Lax-Wendroff update (Eq. 8
 LAW_POWER = 0          # G = kg*S^g (1 + gamma*L), B = kb*S^b
 LAW_ARRHENIUS = 1      # as above times exp(-E/(T+273.15)) (App. A, Eq. A.2 form)
 LAW_MLP = 2            # learned closure
+LAW_POLY = 3           # growth a_1 S + ... + a_k S^k (the polynomial law of Sec. 4.1)
 SOL_LINEAR = 0         # Csat = cs0 + cs1*T
 SOL_EXP = 1            # Csat = cs0*exp(cs1*T)   (App. A, Eq. A.1)
 
 # per-simulation parameter row (NPAR doubles)
-P_KG, P_G, P_KB, P_B, P_GAMMA, P_KG2, P_G2, P_EG, P_EB, P_T0, P_T1, P_TRAMP = range(12)
-NPAR = 12
+P_KG, P_G, P_KB, P_B, P_GAMMA, P_KG2, P_G2, P_EG, P_EB, P_T0, P_T1, P_TRAMP, P_EG2 = range(13)
+NPAR = 13
 
 RHO_C_G_PER_UM3 = 1.11e-12          # crystal density, Table 1
 K_V = math.pi / 4.0                  # cylinder shape factor, Table 1
@@ -150,6 +151,7 @@ class Problem:
     extra: dict = field(default_factory=dict)
     mlp: np.ndarray | None = None      # law == LAW_MLP: float32 closure blob [MLP_NBLOB]
     mlp_precision: int = 0             # MLP_BF16 or MLP_FP64
+    poly: np.ndarray | None = None     # law == LAW_POLY: growth coefficients a_1..a_k per sim [S, k]
 
     @property
     def n_sims(self) -> int:
@@ -185,7 +187,8 @@ class Problem:
                        sol_law=self.sol_law, cs0=self.cs0, cs1=self.cs1, alpha=self.alpha,
                        cfl=self.cfl, dt_max=self.dt_max, t_end=self.t_end,
                        name=self.name + "[subset]", extra=dict(self.extra),
-                       mlp=None if self.mlp is None else self.mlp.copy(), mlp_precision=self.mlp_precision)
+                       mlp=None if self.mlp is None else self.mlp.copy(), mlp_precision=self.mlp_precision,
+                       poly=None if self.poly is None else self.poly[idx].copy())
 
     def with_(self, **kw) -> "Problem":
         d = dict(self.__dict__)
@@ -194,11 +197,12 @@ class Problem:
 
 
 def _par_row(kg, g, kb, b, gamma=0.0, kg2=0.0, g2=0.0, Eg=0.0, Eb=0.0,
-             T0=T_HOT, T1=T_COLD, t_ramp=T_RAMP) -> np.ndarray:
+             T0=T_HOT, T1=T_COLD, t_ramp=T_RAMP, Eg2=None) -> np.ndarray:
     r = np.zeros(NPAR)
     r[P_KG], r[P_G], r[P_KB], r[P_B], r[P_GAMMA] = kg, g, kb, b, gamma
     r[P_KG2], r[P_G2], r[P_EG], r[P_EB] = kg2, g2, Eg, Eb
     r[P_T0], r[P_T1], r[P_TRAMP] = T0, T1, t_ramp
+    r[P_EG2] = Eg if Eg2 is None else Eg2
     return r
 
 
@@ -433,3 +437,40 @@ def cfl_limited(n_sims: int = 24, n_lo: int = 4, n_hi: int = 2048, t_end: float 
                    f0=np.concatenate(seeds), C0=np.array(C0), par=np.array(pars),
                    t_samples=np.array(ts, dtype=np.float64), t_end=t_end, dt_max=dt_max,
                    name=f"cfl-limited-{n_sims}x[{n_lo},{n_hi}]")
+
+
+# ---- the paper's own 2D case (Table 1 and App. A, Table A.1)
+PAPER_RHO_C = 1.11e-12               # g/um^3, Table 1
+PAPER_KV = math.pi / 4.0             # cylinder, Table 1
+
+
+def paper_2d(n1: int = 1200, n2: int = 600, t_end: float = 1000.0, n_samples: int = 4) -> Problem:
+    """The paper's seeded batch crystallization in length x width (Table 1, App. A).
+
+    Growth only (no nucleation), constant temperature 15 degC, exponential
+    solubility c* = 3.37 exp(0.036 T) g/kg, per-axis Arrhenius growth
+    G_m = k_m1 exp(-k_m2/(T + 273.15)) (S - 1)^k_m3 with Table A.1's constants
+    (k_11 = 8.86e6 um/min, k_12 = 2450 K, k_13 = 3.7; k_21 = 4.088e5 um/min,
+    k_22 = 2400 K, k_23 = 2.5), c0 = 8 g/kg, a Gaussian seed (400, 250) +- (30, 30)
+    um scaled to a seed mass of 1 g, domain 1200 x 600 um on n1 x n2 bins, the
+    one-step limited scheme of Eq. (8) at Courant number 0.9 and no cap on the
+    step.  Units of this problem: time in minutes (the rates are in um/min),
+    concentration in g per kg of solvent, number density per um^2 and kg of
+    solvent, so alpha = rho_c k_v.  The printed simulation time "1000 [hour]"
+    is garbled; it is read as 1000 minutes (t_end).
+    """
+    L1, L2 = 1200.0, 600.0
+    f = gaussian_seed_2d(n1, n2, L1, L2, (400.0, 250.0), (30.0, 30.0), 0.0, 1.0)
+    d1, d2 = L1 / n1, L2 / n2
+    x = (np.arange(n1) + 0.5) * d1
+    y = (np.arange(n2) + 0.5) * d2
+    mu12 = float((x[None, :] * (y ** 2)[:, None] * f).sum() * d1 * d2)
+    f = f * (1.0 / (PAPER_RHO_C * PAPER_KV * mu12))   # seed mass rho_c k_v mu_12 = 1 g
+    # kg in the solver's units (1e6 kg is the rate constant in um per time unit)
+    par = _par_row(8.86e6 / 1e6, 3.7, 0.0, 1.0, 0.0, kg2=4.088e5 / 1e6, g2=2.5, Eg=2.45e3, Eb=0.0,
+                   T0=15.0, T1=15.0, t_ramp=0.0, Eg2=2.4e3)
+    return Problem(ndim=2, n_cells=np.array([[n1, n2]], dtype=np.int32), L_max=np.array([[L1, L2]]),
+                   f0=np.ascontiguousarray(f.ravel()), C0=np.array([8.0]), par=par[None, :],
+                   t_samples=uniform_samples(n_samples, t_end), t_end=t_end, law=LAW_ARRHENIUS, sol_law=SOL_EXP,
+                   cs0=3.37, cs1=0.036, alpha=PAPER_RHO_C * PAPER_KV, scheme=SCHEME_LW_TVD, cfl=0.9, dt_max=t_end,
+                   name=f"paper2d-{n1}x{n2}")

@@ -117,8 +117,8 @@ def test_gradient_options_rejected_on_host():
     assert _create_rc(base.with_(scheme=W.SCHEME_LW_TVD), ckpt_every=16) == pbe.PBE_EUNSUPPORTED
     big = W.batched(2, 1500, 1600, t_end=100.0, n_samples=2)
     assert _create_rc(big, ckpt_every=16) == pbe.PBE_EUNSUPPORTED
-    # the 2D split solver is forward-only and runs SSP-RK3 sweeps
+    # the 2D split solver is forward-only and records moments, not densities
     two = W.shape_2d(2, 16, 24, t_end=100.0, n_samples=2)
     assert _create_rc(two, ckpt_every=16) == pbe.PBE_EUNSUPPORTED
     assert _create_rc(two, record_f=True) == pbe.PBE_EUNSUPPORTED
-    assert _create_rc(two.with_(scheme=W.SCHEME_LW_TVD)) == pbe.PBE_EUNSUPPORTED
+    assert _create_rc(two, record_rates=True) == pbe.PBE_EUNSUPPORTED
