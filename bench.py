@@ -251,6 +251,30 @@ def calibrate_copy(mib: int):
                       "copies": 3, "best_ms": min(ms), "copy_GBps": gbs}), flush=True)
 
 
+def paper2d_leg(steps: int):
+    """The paper's own 2D case at its finest grid (workloads.paper_2d: 6000 x 3000 bins of 0.2 um,
+    one-step scheme at Courant 0.9, Arrhenius growth per axis, 1000 min), one simulation.  The paper
+    reports 1339 time steps for this grid and a JAX (RTX 4090) time of roughly a third of 1.2 s."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    from paper_2411_00742_amd import workloads as W
+    prob = W.paper_2d(6000, 3000)
+    solver = pbe.Solver(prob)
+    out = solver.solve()
+    torch.cuda.synchronize()
+    st = int(out["steps"].cpu()[0])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.solve(out)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    solver.close()
+    cu = st * 6000 * 3000
+    return dict(value=cu / el, unit="cell-updates/s", grid="6000 x 3000", steps=st, ms_per_solve=1e3 * el,
+                paper_context="the paper: 1339 steps for this grid in roughly 0.4 s (JAX on an RTX 4090, its Sec. 3.2); "
+                              "context, not a target")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +286,7 @@ def main():
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D leg")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
+    ap.add_argument("--no-paper2d", action="store_true", help="skip the paper's 6000 x 3000 2D case")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first (pbe_tune)")
     ap.add_argument("--steps-closure", type=int, default=3)
     ap.add_argument("--steps-2d", type=int, default=2)
@@ -377,6 +402,9 @@ def main():
     if not args.no_2d:
         result["fvm2d"] = fvm2d_leg(args.steps_2d)
         log(f"[bench] 2D leg: {result['fvm2d']}")
+    if not args.no_paper2d:
+        result["paper2d"] = paper2d_leg(args.steps_2d)
+        log(f"[bench] paper 2D leg: {result['paper2d']}")
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(prob, 16, threads)

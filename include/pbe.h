@@ -47,7 +47,9 @@ enum { PBE_SCHEME_SSPRK3 = 0,   /* method of lines, Shu-Osher SSP-RK3, kappa = 1
        PBE_SCHEME_LW_TVD = 1 }; /* the paper's one-step limited update, Eq. (8) */
 enum { PBE_LAW_POWER = 0,       /* G = kg S^g (1 + gamma L), B = kb S^b, S = C/Csat - 1 */
        PBE_LAW_ARRHENIUS = 1,   /* power law times exp(-Eg/(T+273.15)), exp(-Eb/(T+273.15)) (App. A, Eq. A.2) */
-       PBE_LAW_MLP = 2 };       /* learned closure for (G0, B); see pbe_problem.mlp */
+       PBE_LAW_MLP = 2,         /* learned closure for (G0, B); see pbe_problem.mlp */
+       PBE_LAW_POLY = 3 };      /* G0 = a_1 S + ... + a_k S^k (um/s), B = kb S^b: the polynomial
+                                   growth law of Sec. 4.1, Eq. (poly_growth_rate); see pbe_problem.poly */
 enum { PBE_SOL_LINEAR = 0,      /* Csat = cs0 + cs1 T */
        PBE_SOL_EXP = 1 };       /* Csat = cs0 exp(cs1 T) (App. A, Eq. A.1) */
 /* per-sim status bits written to status_out */
@@ -109,7 +111,11 @@ typedef struct {
     int32_t max_steps;          /* per-sim step budget (0: derived from t_end, dt_max and the CFL bound) */
     int32_t flags;              /* PBE_FLAG_* */
     int32_t mlp_precision;      /* law == PBE_LAW_MLP: PBE_MLP_BF16 or PBE_MLP_FP64 */
+    int32_t n_poly;             /* law == PBE_LAW_POLY: coefficients per sim, k in [1, PBE_MAX_POLY] */
+    const double *poly;         /* law == PBE_LAW_POLY: host [S][n_poly] a_1..a_k, finite and >= 0 (the
+                                   paper's constraint); grids of up to 1024 cells, SSP-RK3 */
 } pbe_problem;
+#define PBE_MAX_POLY 1024
 
 /* Create a handle: validates `p`, deep-copies every input to device memory
  * (the caller may free its buffers on return), orders the sims for the
@@ -164,6 +170,23 @@ int pbe_fetch(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
  * Requires ckpt_every > 0 and a completed pbe_solve (PBE_ESTATE otherwise). */
 int pbe_grad(pbe_handle *h, const double *gf, const double *gmom, const double *gC,
              double *gpar_out, double *gmlp_out);
+
+/* Replace every sim's polynomial growth coefficients (law == PBE_LAW_POLY) with
+ * poly[S][n_poly] (host, or device with PBE_FLAG_DEVICE_PTRS; host values are
+ * checked to be finite and >= 0) and restart from the initial condition.
+ * Waits for the handle's queued work.  PBE_ESTATE for other laws, or (host
+ * pointers, derived step budget) when the new law's step bound exceeds the
+ * budget sized at create. */
+int pbe_set_poly(pbe_handle *h, const double *poly);
+
+/* pbe_grad for the polynomial growth law (Sec. 4.1: the gradient of the
+ * estimation loss with respect to the law's coefficients): the same
+ * vector-Jacobian product of the last solve's outputs, written as
+ *   gpar_out   [S][PBE_NGRAD] as in pbe_grad (kg and g do not enter: 0), may be NULL,
+ *   gpoly_out  [S][n_poly] d<cot, outputs>/d(a_1..a_k) per sim.
+ * Same conditions as pbe_grad; PBE_ESTATE for other laws. */
+int pbe_grad_poly(pbe_handle *h, const double *gf, const double *gmom, const double *gC, double *gpar_out,
+                  double *gpoly_out);
 
 /* Replace the closure weights (law == MLP) with w[PBE_MLP_NW] (host pointer,
  * or device pointer with PBE_FLAG_DEVICE_PTRS; the blob's constants are kept)

@@ -27,7 +27,8 @@ NGRAD = 5
 # every entry point of include/pbe.h
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
            "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_set_launch", "pbe_destroy", "pbe_strerror",
-           "pbe_last_kernel_ms", "pbe_rate_log", "pbe_mlp_vjp", "pbe_mlp_vjp_noalloc"]
+           "pbe_last_kernel_ms", "pbe_rate_log", "pbe_mlp_vjp", "pbe_mlp_vjp_noalloc", "pbe_set_poly",
+           "pbe_grad_poly"]
 MLP_VJP_NOALLOC_MAX_ROWS = 4096
 MLP_NW, MLP_NC = 4546, 18
 MLP_BF16, MLP_FP64 = 0, 1
@@ -44,7 +45,7 @@ class PbeProblem(C.Structure):
                 ("cs0", C.c_double), ("cs1", C.c_double), ("alpha", C.c_double), ("cfl", C.c_double),
                 ("dt_max", C.c_double), ("t_end", C.c_double), ("t_samples", _dp),
                 ("ckpt_every", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_int32),
-                ("mlp_precision", C.c_int32)]
+                ("mlp_precision", C.c_int32), ("n_poly", C.c_int32), ("poly", _dp)]
 
 
 class PbeTuning(C.Structure):
@@ -90,6 +91,8 @@ def lib():
         L.pbe_rate_log.argtypes = [vp, C.c_int32, vp]
         L.pbe_mlp_vjp.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.pbe_mlp_vjp_noalloc.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
+        L.pbe_set_poly.argtypes = [vp, vp]
+        L.pbe_grad_poly.argtypes = [vp, vp, vp, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("pbe_destroy", "pbe_strerror"):
                 getattr(L, name).restype = C.c_int
@@ -115,6 +118,9 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
     mlp = getattr(prob, "mlp", None)
     if mlp is not None:
         keep["mlp"] = _arr(mlp, np.float32)
+    poly = getattr(prob, "poly", None)
+    if poly is not None:
+        keep["poly"] = _arr(poly, np.float64)
     flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0) | \
         (FLAG_AUTOTUNE if autotune else 0) | (FLAG_RECORD_RATES if record_rates else 0)
     st = PbeProblem(ndim=prob.ndim, n_sims=prob.n_sims,
@@ -126,7 +132,9 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
                     cs0=prob.cs0, cs1=prob.cs1, alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max,
                     t_end=prob.t_end, t_samples=keep["t_samples"].ctypes.data_as(_dp),
                     ckpt_every=ckpt_every, max_steps=max_steps, flags=flags,
-                    mlp_precision=int(getattr(prob, "mlp_precision", 0)))
+                    mlp_precision=int(getattr(prob, "mlp_precision", 0)),
+                    n_poly=0 if poly is None else int(keep["poly"].shape[1]),
+                    poly=keep["poly"].ctypes.data_as(_dp) if "poly" in keep else None)
     return st, keep
 
 
@@ -159,6 +167,8 @@ class Solver:
         del keep
         self.S = prob.n_sims
         self.ns = len(prob.t_samples)
+        poly = getattr(prob, "poly", None)
+        self.n_poly = 0 if poly is None else int(np.asarray(poly).shape[1])
         self.total = int(prob.cells_per_sim().sum())
 
     # --- output buffers -------------------------------------------------------
@@ -209,6 +219,26 @@ class Solver:
         cot = [None if x is None else x.to(device=self.device, dtype=t.float64).contiguous() for x in (gf, gmom, gC)]
         _check(lib().pbe_grad(self._h, _ptr(cot[0]), _ptr(cot[1]), _ptr(cot[2]), _ptr(g), _ptr(gw)), "pbe_grad")
         return (g, gw) if with_mlp else g
+
+    def set_poly(self, poly):
+        """New polynomial growth coefficients [S, n_poly] (device tensor or host array)."""
+        self.generation += 1
+        t = self.torch
+        c = t.as_tensor(poly, dtype=t.float64).to(self.device).contiguous()
+        assert c.shape == (self.S, self.n_poly)
+        _check(lib().pbe_set_poly(self._h, _ptr(c)), "pbe_set_poly")
+        self._poly_keep = c
+
+    def grad_poly(self, gf=None, gmom=None, gC=None):
+        """d<cotangents, outputs>/d(polynomial coefficients) per sim [S, n_poly], and the
+        (kg, g, kb, b, gamma) gradient [S, 5] (device tensors)."""
+        t = self.torch
+        g = t.empty((self.S, NGRAD), dtype=t.float64, device=self.device)
+        gp = t.empty((self.S, self.n_poly), dtype=t.float64, device=self.device)
+        cot = [None if x is None else x.to(device=self.device, dtype=t.float64).contiguous() for x in (gf, gmom, gC)]
+        _check(lib().pbe_grad_poly(self._h, _ptr(cot[0]), _ptr(cot[1]), _ptr(cot[2]), _ptr(g), _ptr(gp)),
+               "pbe_grad_poly")
+        return gp, g
 
     def set_mlp(self, w):
         """New closure weights: a float32 device tensor (or array) of MLP_NW values."""

@@ -127,6 +127,9 @@ __device__ __forceinline__ int samples_reached(const double* ts, int ns, double 
     return uniform(n);
 }
 
+// the learned closure (a network) as opposed to the plain or polynomial laws
+constexpr bool is_net(int cl) { return cl == kClosureBf16 || cl == kClosureFp64; }
+
 template <int K, int CL>
 __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* __restrict__ lds) {
     const Fvm1dArgs& a = A.fw;
@@ -181,6 +184,12 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     double* tapeT = A.tape_t + (int64_t)s * Kc;
     double* tapeR = A.tape_r + (int64_t)s * Kc * kClosureTape;
     double* rows = A.rows + (int64_t)s * A.row_cap * 5;
+    // polynomial law: its coefficients, and d/da_j accumulated in LDS after the
+    // stage buffers (lane l owns the exponents j = l + 1 + 64 m, slot m * 64 + l)
+    const double* coef = a.poly + (int64_t)s * a.n_poly;
+    double* ga = lds + 4 * K * 64;
+    const int n_terms = CL == kClosurePoly ? (a.n_poly + 63) >> 6 : 0;
+    for (int m = 0; m < n_terms; ++m) ga[m * 64 + lane] = 0.0;
 
     const int n_seg = (n_total + Kc - 1) / Kc;
     for (int seg = n_seg - 1; seg >= 0; --seg) {
@@ -205,6 +214,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             Rates r;
             if constexpr (CL == kClosureNone) {
                 r = rates_plain(p, q, C, t);
+            } else if constexpr (CL == kClosurePoly) {
+                r = rates_poly<false>(p, q, C, t, coef, a.n_poly, nullptr);
             } else {
                 // closure with the forward tangents d/dz0, d/dz2; taped for the reverse walk
                 LaneGeom g2 = g;
@@ -296,8 +307,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             bool fb = true;        // plain power law at this step
             bool clamped = false;  // closure: ln G0 held at its bound (no derivative through G0)
             double cz[3] = {0.0, 0.0, 0.0}, cj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, cmu2 = 0.0;
+            PolyTerms pt{0.0, 0.0, 0.0};
             if constexpr (CL == kClosureNone) {
                 r = rates_plain(p, q, Cm, tm);
+            } else if constexpr (CL == kClosurePoly) {
+                r = rates_poly<true>(p, q, Cm, tm, coef, a.n_poly, &pt);
             } else {
                 const double* tr = tapeR + (int64_t)(m - 1 - m0) * kClosureTape;
                 const int flags = (int)uniform(tr[0]);
@@ -429,7 +443,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     rw[0] = cz[0]; rw[1] = cz[1]; rw[2] = cz[2]; rw[3] = yb0; rw[4] = yb1;
                 }
             } else if (r.S > 0.0) {
-                const double dGdS = q.g * r.G0 / r.S;
+                const double dGdS = CL == kClosurePoly ? pt.dGdS : q.g * r.G0 / r.S;
                 const double dBdS = q.b * r.B / r.S;
                 const double Sbar = G0b * dGdS + Bb * dBdS;
                 lamC += Sbar / Csat;
@@ -439,12 +453,21 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     const double iT = 1.0 / (Tm + 273.15);
                     Tb += (G0b * r.G0 * q.Eg + Bb * r.B * q.Eb) * (iT * iT);
                 }
-                gk[0] += G0b * 1e6 * r.Sg * r.arrG;
-                gk[1] += G0b * r.G0 * r.lnS;
+                if constexpr (CL == kClosurePoly) {
+                    // dG0/da_j = S^j
+                    double pw = pt.Sl;
+                    for (int mm = 0; mm < n_terms; ++mm) {
+                        ga[mm * 64 + lane] = fma(G0b, pw, ga[mm * 64 + lane]);
+                        pw *= pt.S64;
+                    }
+                } else {
+                    gk[0] += G0b * 1e6 * r.Sg * r.arrG;
+                    gk[1] += G0b * r.G0 * r.lnS;
+                }
                 gk[2] += Bb * r.Sb * r.arrB;
                 gk[3] += Bb * r.B * r.lnS;
             }
-            if (CL != kClosureNone && fb && lane == 0) {
+            if (is_net(CL) && fb && lane == 0) {
                 double* rw = rows + (int64_t)(m - 1) * 5;
                 rw[0] = 0.0; rw[1] = 0.0; rw[2] = 0.0; rw[3] = 0.0; rw[4] = 0.0;
             }
@@ -456,6 +479,12 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     if (lane == 0) {
         double* o = A.gpar + (int64_t)s * PBE_NGRAD;
         o[0] = gk[0]; o[1] = gk[1]; o[2] = gk[2]; o[3] = gk[3]; o[4] = gg;
+    }
+    if constexpr (CL == kClosurePoly) {
+        for (int m = 0; m < n_terms; ++m) {
+            const int j = m * 64 + lane;
+            if (j < a.n_poly) A.gpoly[(int64_t)s * a.n_poly + j] = ga[m * 64 + lane];
+        }
     }
 }
 
@@ -469,7 +498,7 @@ template <int KLO, int CL>
 __global__ __launch_bounds__(64, adj_waves_per_simd(KLO)) void k_adj1d(Adj1dArgs A, int cls_begin, int cls_count, int32_t* queue) {
     // the three SSP-RK3 stage input states of the step being reversed and the
     // direct part of its adjoint (each lane owns its column)
-    __shared__ double lds[4 * (KLO + 7) * 64];
+    __shared__ double lds[4 * (KLO + 7) * 64 + (CL == kClosurePoly ? kMaxPoly : 0)];
     for (;;) {
         const int ticket = atomicAdd(queue, threadIdx.x == 0 ? 1 : 0);
         const int idx = __builtin_amdgcn_readfirstlane(ticket);
@@ -506,6 +535,7 @@ static hipError_t launch_cl(int cls, const Adj1dArgs& A, int n_blocks, int begin
 
 hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st) {
+    if (A.fw.closure == kClosurePoly) return launch_cl<kClosurePoly>(cls, A, n_blocks, begin, count, queue, st);
     if (A.fw.closure == kClosureBf16) return launch_cl<kClosureBf16>(cls, A, n_blocks, begin, count, queue, st);
     if (A.fw.closure == kClosureFp64) return launch_cl<kClosureFp64>(cls, A, n_blocks, begin, count, queue, st);
     return launch_cl<kClosureNone>(cls, A, n_blocks, begin, count, queue, st);
@@ -523,6 +553,7 @@ int adj1d_class_resident_blocks(int cls, int closure) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const hipError_t e = closure == kClosureBf16   ? adj_occupancy<kClosureBf16>(cls, &per_cu)
                          : closure == kClosureFp64 ? adj_occupancy<kClosureFp64>(cls, &per_cu)
+                         : closure == kClosurePoly ? adj_occupancy<kClosurePoly>(cls, &per_cu)
                                                    : adj_occupancy<kClosureNone>(cls, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);

@@ -70,6 +70,8 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         Rates r;
         if constexpr (CL == kClosureNone) {
             r = rates_plain(p, q, C, t);
+        } else if constexpr (CL == kClosurePoly) {
+            r = rates_poly<false>(p, q, C, t, a.poly + (int64_t)s * a.n_poly, a.n_poly, nullptr);
         } else {
             // learned closure: inputs S, T and mu_2 of the current state
             LaneGeom g2 = g;
@@ -170,7 +172,8 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
 // simulation of a 4096-simulation batch fits the device at once) and the
 // 9-16 class at 2
 constexpr int fvm_waves_per_simd(int klo, int cl) {
-    return cl != 0 ? (klo == 1 ? 4 : 2) : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
+    return (cl == kClosureBf16 || cl == kClosureFp64) ? (klo == 1 ? 4 : 2)
+                                                      : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
 }
 
 // run simulation s with its K (uniform) in [KA, KHI]: a chain of scalar branches
@@ -285,6 +288,7 @@ static hipError_t launch_closure_class(int cls, const Fvm1dArgs& a, int n_blocks
 
 hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st) {
+    if (a.closure == kClosurePoly) return launch_closure_class<kClosurePoly>(cls, a, n_blocks, begin, count, queue, st);
     if (a.closure == kClosureBf16) return launch_closure_class<kClosureBf16>(cls, a, n_blocks, begin, count, queue, st);
     if (a.closure == kClosureFp64) return launch_closure_class<kClosureFp64>(cls, a, n_blocks, begin, count, queue, st);
     if (a.scheme == PBE_SCHEME_LW_TVD) return launch_class<PBE_SCHEME_LW_TVD>(cls, a, n_blocks, begin, count, queue, st);
@@ -315,6 +319,7 @@ int fvm1d_class_resident_blocks(int cls, int closure, int pairs) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const hipError_t e = closure == kClosureBf16   ? occupancy<kClosureBf16>(cls, pairs, &per_cu)
                          : closure == kClosureFp64 ? occupancy<kClosureFp64>(cls, pairs, &per_cu)
+                         : closure == kClosurePoly ? occupancy<kClosurePoly>(cls, pairs, &per_cu)
                                                    : occupancy<kClosureNone>(cls, pairs, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);

@@ -174,6 +174,53 @@ __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& 
     return r;
 }
 
+// Rates of the polynomial growth law (Sec. 4.1, Eq. (poly_growth_rate)):
+// G0 = a_1 S + ... + a_k S^k for S = C/Csat - 1 > 0 (the a_j in um/s), with
+// nucleation kb S^b.  Lane l sums the terms of the exponents j = l + 1 + 64 m
+// (Horner in S^64 over m) and the wave adds the lanes up, so k up to 1024
+// costs at most 16 steps per lane.  DER: also dG0/dS, and the per-lane S^(l+1)
+// and S^64 from which the adjoint forms each coefficient's derivative S^j.
+struct PolyTerms {
+    double dGdS, Sl, S64;
+};
+template <bool DER>
+__device__ __forceinline__ Rates rates_poly(const Process& p, const SimParams& q, double C, double t,
+                                            const double* a, int k, PolyTerms* pt) {
+    Rates r;
+    const double T = temperature(q, t);
+    r.S = div_fast(C, solubility(p, T)) - 1.0;
+    r.G0 = 0.0; r.B = 0.0; r.lnS = 0.0; r.arrG = 1.0; r.arrB = 1.0; r.Sg = 0.0; r.Sb = 0.0;
+    double dG = 0.0, Sl = 0.0, S64 = 0.0;
+    if (r.S > 0.0) {
+        const int lane = threadIdx.x & 63;
+        r.lnS = log64(r.S);
+        Sl = exp64((double)(lane + 1) * r.lnS);
+        S64 = uniform(exp64(64.0 * r.lnS));
+        const int M = (k + 63) >> 6;
+        double acc = 0.0, dacc = 0.0;
+        for (int m = M - 1; m >= 0; --m) {
+            const int j = lane + 64 * m;
+            const double aj = a[min(j, k - 1)];
+            const double am = j < k ? aj : 0.0;
+            acc = fma(acc, S64, am);
+            if (DER) dacc = fma(dacc, S64, (double)(j + 1) * am);
+        }
+        r.G0 = wave_sum(Sl * acc);
+        if (DER) dG = div_fast(wave_sum(Sl * dacc), r.S);
+        r.Sb = exp64(q.b * r.lnS);
+        r.B = q.kb * r.Sb;
+    }
+    r.G0 = uniform(r.G0);
+    r.B = uniform(r.B);
+    r.S = uniform(r.S);
+    if (DER) {
+        pt->dGdS = uniform(dG);
+        pt->Sl = Sl;
+        pt->S64 = S64;
+    }
+    return r;
+}
+
 // Rates of the 2D model: growth along each axis (G1 with kg, g; G2 with kg2, g2)
 // and nucleation, all driven by the same supersaturation.
 struct Rates2 {

@@ -102,7 +102,11 @@ struct pbe_handle {
     int resident[2][kFvmClasses] = {};  // 1D: workgroups of each class that fit at once [pairs][class]
     std::vector<double> cost;        // 1D: estimated work per sim (launch order within a class)
     std::vector<double> C0h, mu3h, Lmaxh;  // 1D: host copies for re-deriving the step bound (pbe_set_par)
+    std::vector<double> par_host;          // 1D: the current parameter rows (host copy)
     double lnG0_max = 0.0;           // closure: clamp on the network's ln G0
+    double* d_poly = nullptr;        // polynomial law: [S][n_poly] coefficients
+    double* d_gpoly = nullptr;       // polynomial law: [S][n_poly] their gradient (ckpt_every > 0)
+    std::vector<double> poly_host;   // host copy for re-deriving the step bound
     bool derived_cap = false;        // step_cap was derived from the step bound (max_steps == 0)
     std::vector<int32_t> active_host;
     bool fresh = true;               // next pbe_step starts from the initial condition
@@ -135,7 +139,8 @@ int validate(const pbe_problem* p) {
     if (p->ndim == 2) return validate2d(p);
     if (p->ndim != 1) return PBE_EINVAL;
     if (p->n_sims < 1 || !p->n_cells || !p->L_max || !p->f0 || !p->C0 || !p->par || !p->t_samples) return PBE_EINVAL;
-    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS && p->law != PBE_LAW_MLP) return PBE_EINVAL;
+    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS && p->law != PBE_LAW_MLP && p->law != PBE_LAW_POLY)
+        return PBE_EINVAL;
     if (p->scheme != PBE_SCHEME_SSPRK3 && p->scheme != PBE_SCHEME_LW_TVD) return PBE_EINVAL;
     if (p->sol_law != PBE_SOL_LINEAR && p->sol_law != PBE_SOL_EXP) return PBE_EINVAL;
     if (!is_finite(p->cs0) || !is_finite(p->cs1) || !is_finite(p->alpha) || p->alpha < 0.0) return PBE_EINVAL;
@@ -148,6 +153,14 @@ int validate(const pbe_problem* p) {
         if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
     }
     if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
+    if (p->law == PBE_LAW_POLY) {
+        if (p->n_poly < 1 || p->n_poly > PBE_MAX_POLY || !p->poly) return PBE_EINVAL;
+        for (int64_t i = 0; i < (int64_t)p->n_sims * p->n_poly; ++i)
+            if (!is_finite(p->poly[i]) || p->poly[i] < 0.0) return PBE_EINVAL;
+        if (p->scheme != PBE_SCHEME_SSPRK3) return PBE_EUNSUPPORTED;
+        for (int s = 0; s < p->n_sims; ++s)
+            if (p->n_cells[s] > kWave * 8 * kAdjClasses) return PBE_EUNSUPPORTED;
+    }
     if (p->law == PBE_LAW_MLP) {
         const int rc = validate_closure(p);
         if (rc != PBE_OK) return rc;
@@ -184,7 +197,8 @@ int validate(const pbe_problem* p) {
 
 int validate_common(const pbe_problem* p) {
     if (p->n_sims < 1 || !p->n_cells || !p->L_max || !p->f0 || !p->C0 || !p->par || !p->t_samples) return PBE_EINVAL;
-    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return p->law == PBE_LAW_MLP ? PBE_EUNSUPPORTED : PBE_EINVAL;
+    if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS)
+        return (p->law == PBE_LAW_MLP || p->law == PBE_LAW_POLY) ? PBE_EUNSUPPORTED : PBE_EINVAL;
     if (p->scheme != PBE_SCHEME_SSPRK3 && p->scheme != PBE_SCHEME_LW_TVD) return PBE_EINVAL;
     if (p->sol_law != PBE_SOL_LINEAR && p->sol_law != PBE_SOL_EXP) return PBE_EINVAL;
     if (!is_finite(p->cs0) || !is_finite(p->cs1) || !is_finite(p->alpha) || p->alpha < 0.0) return PBE_EINVAL;
@@ -247,13 +261,22 @@ double seed_mu3(int n, double Lmax, const double* f0) {
 // solute inventory C + alpha*mu3 allows at the lowest solubility.  With the
 // learned closure G0 is also bounded by exp(lnG0_max) (the network's clamp)
 // and the plain law stands in outside its box, so the larger of both bounds.
-double step_bound(const pbe_problem* p, const double* q, int n, double Lmax, double C0, double mu3, double lnG0_max) {
+double step_bound(const pbe_problem* p, const double* q, int n, double Lmax, double C0, double mu3, double lnG0_max,
+                  const double* poly = nullptr) {
     const double dL = Lmax / n;
     const double csat_min = std::min(solubility(p, q[PBE_P_T0]), solubility(p, q[PBE_P_T1]));
     const double Smax = std::max(0.0, (C0 + p->alpha * mu3) / csat_min - 1.0);
     // (the Arrhenius factor exp(-Eg/(T+273.15)) is at most 1 for Eg >= 0)
     double G0max = 1e6 * q[PBE_P_KG] * std::pow(Smax, q[PBE_P_G]);
     if (p->law == PBE_LAW_MLP) G0max = std::max(G0max, std::exp(lnG0_max));
+    if (p->law == PBE_LAW_POLY) {   // sum of a_j Smax^j with a_j >= 0
+        G0max = 0.0;
+        double Sj = Smax;
+        for (int j = 0; j < p->n_poly; ++j) {
+            G0max += poly[j] * Sj;
+            Sj *= Smax;
+        }
+    }
     const double Gmax = G0max * (1.0 + q[PBE_P_GAMMA] * Lmax);
     double dt_min = p->dt_max;
     if (Gmax > 0.0) dt_min = std::min(dt_min, p->cfl * dL / Gmax);
@@ -837,6 +860,7 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     // step budget and launch order: class by cells per lane, longest first within a class
     std::vector<double> bound(h->S), cost(h->S);
     h->C0h.assign(p->C0, p->C0 + h->S);
+    h->par_host.assign(p->par, p->par + (size_t)h->S * PBE_NPAR);
     h->Lmaxh.assign(p->L_max, p->L_max + h->S);
     h->mu3h.resize(h->S);
     h->lnG0_max = p->law == PBE_LAW_MLP ? (double)p->mlp[PBE_MLP_NW + 17] : 0.0;
@@ -844,7 +868,7 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     for (int s = 0; s < h->S; ++s) {
         h->mu3h[s] = seed_mu3(h->ncell[s], p->L_max[s], p->f0 + h->off[s]);
         bound[s] = step_bound(p, p->par + (size_t)s * PBE_NPAR, h->ncell[s], p->L_max[s], p->C0[s], h->mu3h[s],
-                              h->lnG0_max);
+                              h->lnG0_max, p->law == PBE_LAW_POLY ? p->poly + (size_t)s * p->n_poly : nullptr);
         cap = std::max(cap, bound[s]);
         const double* q = p->par + (size_t)s * PBE_NPAR;
         const double dL = p->L_max[s] / h->ncell[s];
@@ -901,6 +925,15 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     }
     a.rate_log = (p->flags & PBE_FLAG_RECORD_RATES) ? m.get<double>((size_t)S * step_cap * 3) : nullptr;
     a.closure = kClosureNone;
+    a.n_poly = 0;
+    if (p->law == PBE_LAW_POLY) {
+        a.closure = kClosurePoly;
+        a.n_poly = p->n_poly;
+        h->d_poly = m.get<double>((size_t)S * p->n_poly);
+        a.poly = h->d_poly;
+        h->poly_host.assign(p->poly, p->poly + (size_t)S * p->n_poly);
+        if (p->ckpt_every > 0) h->d_gpoly = m.get<double>((size_t)S * p->n_poly);
+    }
     if (p->law == PBE_LAW_MLP) {
         a.closure = p->mlp_precision == PBE_MLP_FP64 ? kClosureFp64 : kClosureBf16;
         h->d_blob = m.get<float>(PBE_MLP_NW + PBE_MLP_NC);
@@ -933,7 +966,10 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         hipMemcpy(d_C0, p->C0, sizeof(double) * S, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_f0, p->f0, sizeof(double) * h->total, hipMemcpyHostToDevice) != hipSuccess)
         return fail(h, PBE_EDEVICE);
-    if (a.closure != kClosureNone) {
+    if (a.closure == kClosurePoly &&
+        hipMemcpy(h->d_poly, p->poly, sizeof(double) * (size_t)S * p->n_poly, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(h, PBE_EDEVICE);
+    if (a.closure == kClosureBf16 || a.closure == kClosureFp64) {
         if (hipMemcpy(h->d_blob, p->mlp, sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), hipMemcpyHostToDevice) !=
                 hipSuccess ||
             pack_closure(h->d_blob, h->d_pack, p->mlp_precision, &a.cd, h->stream) != hipSuccess ||
@@ -1082,7 +1118,8 @@ int pbe_set_par(pbe_handle* h, const double* par) {
     if (!h->two_d && h->derived_cap) {
         for (int s = 0; s < h->S; ++s) {
             const double b = step_bound(&h->p, par + (size_t)s * PBE_NPAR, h->ncell[s], h->Lmaxh[s], h->C0h[s],
-                                        h->mu3h[s], h->lnG0_max);
+                                        h->mu3h[s], h->lnG0_max,
+                                        h->poly_host.empty() ? nullptr : h->poly_host.data() + (size_t)s * h->p.n_poly);
             if (b > (double)h->a.step_cap) return PBE_ESTATE;
         }
     }
@@ -1092,6 +1129,7 @@ int pbe_set_par(pbe_handle* h, const double* par) {
     HIP_OK(hipMemcpyAsync(const_cast<double*>(dpar), par, sizeof(double) * h->S * PBE_NPAR, hipMemcpyHostToDevice,
                           h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
+    if (!h->two_d) h->par_host.assign(par, par + (size_t)h->S * PBE_NPAR);
     h->fresh = true;
     h->solved = false;
     return PBE_OK;
@@ -1099,7 +1137,7 @@ int pbe_set_par(pbe_handle* h, const double* par) {
 
 int pbe_set_mlp(pbe_handle* h, const float* w) {
     if (!h || !w) return PBE_EINVAL;
-    if (h->two_d || h->a.closure == kClosureNone) return PBE_ESTATE;
+    if (h->two_d || !(h->a.closure == kClosureBf16 || h->a.closure == kClosureFp64)) return PBE_ESTATE;
     const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
     if (!dev)
         for (int i = 0; i < PBE_MLP_NW; ++i)
@@ -1223,10 +1261,57 @@ int pbe_adam(float* w, float* m, float* v, const double* g, int32_t n, int32_t s
     return PBE_OK;
 }
 
+namespace {
+int run_adjoint(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
+                double* gmlp_out, double* gpoly_out);
+}
+
 int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
              double* gmlp_out) {
     if (!h) return PBE_EINVAL;
     if (h->two_d) return PBE_EUNSUPPORTED;
+    return run_adjoint(h, gf, gmom, gC, gpar_out, gmlp_out, nullptr);
+}
+
+int pbe_grad_poly(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
+                  double* gpoly_out) {
+    if (!h) return PBE_EINVAL;
+    if (h->two_d) return PBE_EUNSUPPORTED;
+    if (h->a.closure != kClosurePoly) return PBE_ESTATE;
+    return run_adjoint(h, gf, gmom, gC, gpar_out, nullptr, gpoly_out);
+}
+
+int pbe_set_poly(pbe_handle* h, const double* poly) {
+    if (!h || !poly) return PBE_EINVAL;
+    if (h->two_d || h->a.closure != kClosurePoly) return PBE_ESTATE;
+    const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
+    const size_t n = (size_t)h->S * h->a.n_poly;
+    if (!dev) {
+        for (size_t i = 0; i < n; ++i)
+            if (!is_finite(poly[i]) || poly[i] < 0.0) return PBE_EINVAL;
+        if (h->derived_cap)
+            for (int s = 0; s < h->S; ++s) {
+                const double b = step_bound(&h->p, h->par_host.data() + (size_t)s * PBE_NPAR, h->ncell[s], h->Lmaxh[s],
+                                            h->C0h[s], h->mu3h[s], h->lnG0_max, poly + (size_t)s * h->a.n_poly);
+                if (b > (double)h->a.step_cap) return PBE_ESTATE;
+            }
+    }
+    // queued work may still read the coefficients
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_poly, poly, sizeof(double) * n, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (!dev) h->poly_host.assign(poly, poly + n);
+    h->fresh = true;
+    h->solved = false;
+    return PBE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int run_adjoint(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
+                double* gmlp_out, double* gpoly_out) {
     if (h->p.ckpt_every <= 0 || !h->solved) return PBE_ESTATE;
     const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1256,6 +1341,7 @@ int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* 
     A.tape_r = h->d_tapeR;
     A.rows = h->d_rows;
     A.row_cap = h->row_cap;
+    A.gpoly = h->d_gpoly;
     HIP_OK(hipEventRecord(h->ev_g0, h->stream));
     HIP_OK(launch_reset_counter(h->d_queue, kFvmClasses, h->stream));
     HIP_OK(hipEventRecord(h->ev_fork, h->stream));
@@ -1269,18 +1355,24 @@ int pbe_grad(pbe_handle* h, const double* gf, const double* gmom, const double* 
             HIP_OK(hipStreamWaitEvent(h->stream, h->ev_join[c], 0));
         }
     }
-    if (h->a.closure != kClosureNone)
+    if (h->a.closure == kClosureBf16 || h->a.closure == kClosureFp64)
         HIP_OK(launch_closure_grad(h->a.cd, h->d_rows, h->a.step, h->S, h->row_cap, h->d_partial, h->n_partial,
                                    h->d_gmlp, h->stream));
     HIP_OK(hipEventRecord(h->ev_g1, h->stream));
     h->timed_grad = true;
     int rc = copy_out(h, gpar_out, h->d_gpar, sizeof(double) * (size_t)h->S * PBE_NGRAD);
-    if (rc == PBE_OK && gmlp_out && h->a.closure != kClosureNone)
+    if (rc == PBE_OK && gmlp_out && (h->a.closure == kClosureBf16 || h->a.closure == kClosureFp64))
         rc = copy_out(h, gmlp_out, h->d_gmlp, sizeof(double) * PBE_MLP_NW);
+    if (rc == PBE_OK && gpoly_out && h->a.closure == kClosurePoly)
+        rc = copy_out(h, gpoly_out, h->d_gpoly, sizeof(double) * (size_t)h->S * h->a.n_poly);
     if (rc == PBE_OK) rc = leave(h);
     if (rc == PBE_OK && !dev) HIP_OK(hipStreamSynchronize(h->stream));
     return rc;
 }
+
+}  // namespace
+
+extern "C" {
 
 int pbe_rate_log(pbe_handle* h, int32_t n_steps, double* out) {
     if (!h || !out) return PBE_EINVAL;

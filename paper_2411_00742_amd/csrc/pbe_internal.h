@@ -30,8 +30,10 @@ struct ClosureDev {
     int32_t pad_;
 };
 
-// closure variants of the 1D kernels
-enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2 };
+// rate-law variants of the 1D kernels: the plain laws, the learned closure
+// (bf16 or fp64 network) and the polynomial growth law
+enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2, kClosurePoly = 3 };
+constexpr int kMaxPoly = 1024;   // polynomial coefficients per simulation
 
 // Everything the 1D forward kernel reads or writes.  Device pointers only.
 struct Fvm1dArgs {
@@ -73,6 +75,8 @@ struct Fvm1dArgs {
     int32_t closure;           // kClosure*: which rate law the kernels run
     ClosureDev cd;             // closure == kClosureBf16 / kClosureFp64
     double* rate_log;          // [S][step_cap][3] (dt, G0, B) of every step, or null
+    const double* poly;        // closure == kClosurePoly: [S][n_poly] growth coefficients a_1..a_k
+    int32_t n_poly, pad1_;
 };
 
 // Adjoint of the 1D solve (reverse sweep over checkpointed segments).
@@ -89,6 +93,7 @@ struct Adj1dArgs {
     double* rows;              // [S * row_cap * 5] per-step (z0, z1, z2, ybar0, ybar1) for the weight gradient
     int32_t row_cap;           // rows per simulation (>= step_cap, multiple of 16)
     int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
+    double* gpoly;             // polynomial law: [S][n_poly] d/d(a_1..a_k) output
 };
 // per taped step: flags (1 = fallback, 2 = ln G0 clamped), G0, B, z0, z1, z2,
 // dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2

@@ -121,3 +121,34 @@ def test_outflow_through_both_far_edges(torch_cuda, oracle):
         assert r["status"] & 2, r["status"]
         assert int(g["status"][i]) == r["status"], (i, g["status"][i], r["status"])
     compare(p, g, range(p.n_sims), oracle)
+
+
+# --------------------------------------------------------------------------- the paper's own case
+def test_paper_case_against_oracle(torch_cuda, oracle):
+    """The paper's 2D case (Table 1, App. A; workloads.paper_2d): growth only, per-axis Arrhenius
+    growth, exponential solubility, 15 degC, the one-step scheme of Eq. (8) at Courant 0.9 with no
+    cap on the step, over the whole horizon, on coarse grids compared cell by cell."""
+    for n1, n2 in [(240, 120), (600, 300)]:
+        p = W.paper_2d(n1, n2)
+        g = run_gpu(p)
+        compare(p, g, [0], oracle)
+
+
+def test_paper_case_full_size_against_stored_oracle(torch_cuda):
+    """The same case up to the paper's finest grid, 6000 x 3000 bins of 0.2 um (1.8e7 cells): the
+    step count (the quantity the paper reports for this grid, 1339 in its run) must equal the
+    oracle's, and the moments and concentration at the samples match to 1e-10.  The oracle's
+    values are stored in tests/golden/paper2d_oracle.json (written by make_paper2d.py, about a
+    quarter of an hour of CPU time for the largest grid)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper2d_oracle.json")
+    gold = json.load(open(path))
+    for case in gold["cases"]:
+        p = W.paper_2d(case["n1"], case["n2"])
+        g = run_gpu(p)
+        print(case["n1"], case["n2"], "steps gpu", int(g["steps"][0]), "oracle", case["steps"])
+        assert int(g["steps"][0]) == case["steps"]
+        assert int(g["status"][0]) == case["status"]
+        assert rel_each(g["mom"][0], np.array(case["mom"])) <= TOL
+        assert rel_each(g["C"][0], np.array(case["C"])) <= TOL
