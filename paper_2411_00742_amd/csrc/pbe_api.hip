@@ -1296,8 +1296,10 @@ int pbe_set_poly(pbe_handle* h, const double* poly) {
                 if (b > (double)h->a.step_cap) return PBE_ESTATE;
             }
     }
-    // queued work may still read the coefficients
+    // queued work may still read the coefficients; a device source is ordered
+    // after the caller's stream
     HIP_OK(hipStreamSynchronize(h->stream));
+    if (enter(h) != PBE_OK) return PBE_EDEVICE;
     HIP_OK(hipMemcpyAsync(h->d_poly, poly, sizeof(double) * n, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
