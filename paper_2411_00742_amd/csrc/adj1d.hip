@@ -121,10 +121,17 @@ __device__ __forceinline__ void stage_fwd(double (&u)[K], const double (&u0)[K],
     (void)fvm_stage<K, PBE_SCHEME_SSPRK3>(u, u0, g, c, ghost, wa, wb, first);
 }
 
+// number of sample times at or before t (the times ascend strictly): binary
+// search, once per checkpoint segment; within a segment the count advances
+// one sample at a time, as in the forward loop
 __device__ __forceinline__ int samples_reached(const double* ts, int ns, double t) {
-    int n = 0;
-    for (int q = 0; q < ns; ++q) n += (ts[q] <= t) ? 1 : 0;
-    return uniform(n);
+    int lo = 0, hi = ns;   // ts[0..lo) <= t < ts[hi..ns)
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (uniform(ts[mid]) <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    return uniform(lo);
 }
 
 // the learned closure (a network) as opposed to the plain or polynomial laws
@@ -170,13 +177,24 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     double gam = 0.0;    // per lane: gamma through the face weights
     double gams = 0.0;   // wave-uniform: gamma through the CFL step
     int qs = ns - 1;   // next sample (from the end) whose cotangent is still to be added
-    // step index of sample qs, and the bracket of sample times around the
-    // reverse walk's current time (nx samples lie at or before it; t_lo is the
-    // last of them, t_hi the next): carried across steps and reloaded only
-    // when they change, so no step waits on a memory round trip for them
-    int qstep = qs >= 0 ? uniform(a.samp_step[(int64_t)s * ns + qs]) : -1;
+    // step index and cotangents of sample qs, and the bracket of sample times
+    // around the reverse walk's current time (nx samples lie at or before it;
+    // t_lo is the last of them, t_lo2 the one before, t_hi the next): carried
+    // across steps and loaded one sample ahead of their use, so no step waits
+    // on a memory round trip for them
+    int qstep = -1;
+    double q_gc = 0.0, q_gm[4] = {0.0, 0.0, 0.0, 0.0};
+    auto load_sample = [&](int qq) {
+        const int64_t o = (int64_t)s * ns + qq;
+        qstep = uniform(a.samp_step[o]);
+        q_gc = A.gC ? uniform(A.gC[o]) : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q_gm[j] = A.gmom ? uniform(A.gmom[o * 4 + j]) : 0.0;
+    };
+    if (qs >= 0) load_sample(qs);
     int nx = ns;
     double t_lo = ns > 0 ? uniform(ts[ns - 1]) : -__builtin_huge_val();
+    double t_lo2 = ns > 1 ? uniform(ts[ns - 2]) : -__builtin_huge_val();
     double t_hi = p.t_end;
 
     double* tape = A.tape + base * Kc;
@@ -248,7 +266,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             mu3_old = mu3;
             t = uniform(hit ? t_next : t + dt);
             if (hit) {
-                next = samples_reached(ts, ns, t);
+                while (next < ns && uniform(ts[next]) <= t) ++next;
                 t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
             }
         }
@@ -270,14 +288,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             }
             // cotangents of the samples taken at state m
             while (qs >= 0 && qstep == m) {
-                const int64_t o = (int64_t)s * ns + qs;
-                const double gc = A.gC ? A.gC[o] : 0.0;
-                lamC += gc;
-                double gm4[4] = {0.0, 0.0, 0.0, 0.0};
-                if (A.gmom) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) gm4[j] = A.gmom[o * 4 + j];
-                }
+                lamC += q_gc;
+                const double gm4[4] = {q_gm[0], q_gm[1], q_gm[2], q_gm[3]};
                 LaneGeom g3 = g;
                 asm volatile("" : "+v"(g3.xb));
                 double gcell[K];
@@ -294,14 +306,16 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     lam[k] += x > 0.0 ? add : 0.0;
                 }
                 --qs;
-                qstep = qs >= 0 ? uniform(a.samp_step[(int64_t)s * ns + qs]) : -1;
+                if (qs >= 0) load_sample(qs);
+                else qstep = -1;
             }
 
             // samples reached at tm (the forward's sample index at step m-1)
             while (nx > 0 && t_lo > tm) {
                 --nx;
                 t_hi = t_lo;
-                t_lo = nx > 0 ? uniform(ts[nx - 1]) : -__builtin_huge_val();
+                t_lo = t_lo2;
+                t_lo2 = nx > 1 ? uniform(ts[nx - 2]) : -__builtin_huge_val();
             }
             Rates r;
             bool fb = true;        // plain power law at this step
