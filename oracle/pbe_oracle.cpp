@@ -104,12 +104,13 @@ template <int ND> Dual<ND> power(const Dual<ND>& x, const Dual<ND>& p) {
 // ---------------------------------------------------------------------------
 // Process and kinetics.
 // ---------------------------------------------------------------------------
-enum { K_KG, K_G, K_KB, K_B, K_GAMMA, K_KG2, K_G2, K_EG, K_EB, K_T0, K_T1, K_TRAMP, K_EG2 };
+enum { K_KG, K_G, K_KB, K_B, K_GAMMA, K_KG2, K_G2, K_EG, K_EB, K_T0, K_T1, K_TRAMP, K_EG2, K_KD, K_D };
 
 template <class R>
 struct Kinetics {
     R kg, g, kb, b, gamma, kg2, g2;
     double Eg, Eb, Eg2;
+    double kd, d;           // dissolution (S < 0): G0 = -1e6 kd (-S)^d
     std::vector<R> poly;   // a_1..a_k of the polynomial growth law
 };
 
@@ -119,6 +120,7 @@ Kinetics<R> load_kinetics(const double* par) {
     k.kg = R(par[K_KG]); k.g = R(par[K_G]); k.kb = R(par[K_KB]); k.b = R(par[K_B]);
     k.gamma = R(par[K_GAMMA]); k.kg2 = R(par[K_KG2]); k.g2 = R(par[K_G2]);
     k.Eg = par[K_EG]; k.Eb = par[K_EB]; k.Eg2 = par[K_EG2];
+    k.kd = par[K_KD]; k.d = par[K_D];
     return k;
 }
 
@@ -188,6 +190,18 @@ void rate_laws(int law, const Kinetics<R>& k, const Q& T, R Sp, R& G0, R& G2, R&
         }
         G2 = R(0.0);
     }
+}
+
+// Dissolution: in an undersaturated solution (C < Csat) the crystals of the
+// power and Arrhenius laws shrink at G0 = -1e6 kd (1 - C/Csat)^d um/s; the
+// paper names the growth/dissolution rate of each axis without a law for the
+// latter, so this one mirrors the growth power law.  Zero when kd = 0 or
+// C >= Csat.
+template <class R, class Q>
+R dissolution_rate(const Kinetics<R>& k, const R& C, const Q& Csat) {
+    const R under = 1.0 - C / Csat;
+    if (!(val(under) > 0.0) || !(k.kd > 0.0)) return R(0.0);
+    return -1e6 * k.kd * power(under, R(k.d));
 }
 
 // ---------------------------------------------------------------------------
@@ -325,31 +339,42 @@ R limited_slope(const R& a, const R& b) {
 // One-dimensional finite-volume building blocks.
 // ---------------------------------------------------------------------------
 // Face fluxes F[j], j = 0..n, where face j separates cells j-1 and j and sits
-// at L = j*dL.  Growth moves crystals to larger sizes, so the upwind cell of
-// face j is i = j-1.  Ghost cells: i = -1 and i = -2 hold `inflow` (set so that
-// G(0)*inflow is the nucleation flux at L = 0), i = n holds 0 (f -> 0 for large
-// L, Sec. 2.1 Eqs. (4)-(6)).
+// at L = j*dL.  Growth (G0 > 0) moves crystals to larger sizes, so the upwind
+// cell of face j is i = j-1.  Ghost cells: i = -1 and i = -2 hold `inflow` (set
+// so that G(0)*inflow is the nucleation flux at L = 0), i = n holds 0 (f -> 0
+// for large L, Sec. 2.1 Eqs. (4)-(6)).
 //   F[j] = vel_j * (f_i + kappa_j/2 * psi(f_i - f_{i-1}, f_{i+1} - f_i))
 // with vel_j = G0 (1 + gamma L_j); kappa = 1 for the method-of-lines form and
-// kappa = 1 - vel_j dt/dL for the one-step update of Eq. (8).
+// kappa = 1 - |vel_j| dt/dL for the one-step update of Eq. (8).
+// Dissolution (G0 < 0) moves crystals to smaller sizes: the upwind cell of
+// face j is i = j, its slope pair is taken on that side, and the ghosts are 0
+// at i = -1 (what crosses L = 0 has dissolved) and at i = n, n+1 (nothing
+// enters through L_max):
+//   F[j] = vel_j * (f_j - kappa_j/2 * psi(f_j - f_{j-1}, f_{j+1} - f_j)).
 template <class R>
 void face_fluxes(const std::vector<R>& u, int n, double dL, const R& G0, const R& gamma, const R& inflow,
                  int scheme, const R& dt, std::vector<R>& F) {
-    std::vector<R> e(n + 3);           // e[i + 2] is cell i, i = -2..n
-    e[0] = inflow;
-    e[1] = inflow;
+    std::vector<R> e(n + 4);           // e[i + 2] is cell i, i = -2..n+1
+    const bool shrink = val(G0) < 0.0;
+    e[0] = shrink ? R(0.0) : inflow;
+    e[1] = shrink ? R(0.0) : inflow;
     for (int i = 0; i < n; ++i) e[i + 2] = u[i];
     e[n + 2] = R(0.0);
+    e[n + 3] = R(0.0);
     for (int j = 0; j <= n; ++j) {
-        const int i = j - 1;
-        const R fi = e[i + 2];
-        const R a = fi - e[i + 1];
-        const R b = e[i + 3] - fi;
-        const R psi = limited_slope(a, b);
         const R vel = G0 * (1.0 + gamma * (j * dL));
         R kappa(1.0);
-        if (scheme == REF_SCHEME_LW_TVD) kappa = 1.0 - vel * (dt / dL);
-        F[j] = vel * (fi + 0.5 * kappa * psi);
+        if (scheme == REF_SCHEME_LW_TVD) kappa = 1.0 - fabs(vel) * (dt / dL);
+        if (!shrink) {
+            const int i = j - 1;
+            const R fi = e[i + 2];
+            const R psi = limited_slope(fi - e[i + 1], e[i + 3] - fi);
+            F[j] = vel * (fi + 0.5 * kappa * psi);
+        } else {
+            const R fj = e[j + 2];
+            const R psi = limited_slope(fj - e[j + 1], e[j + 3] - fj);
+            F[j] = vel * (fj - 0.5 * kappa * psi);
+        }
     }
 }
 
@@ -491,6 +516,10 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
             if (closure_rates(*net, k, C / Csat - 1.0, T, moment1d(f, n, dL, 2), G0, B)) status |= REF_SIM_FALLBACK;
         } else {
             rate_laws(p->law, k, T, Sp, G0, G2, B);
+            if (p->law == REF_LAW_POWER || p->law == REF_LAW_ARRHENIUS) {
+                const R Gd = dissolution_rate(k, C, Csat);
+                if (val(Gd) < 0.0) G0 = Gd;
+            }
         }
         // rates handed in from elsewhere (checks the finite-volume part on its own)
         if (s->G0_replay && s->B_replay && step < s->n_rates_replay) {
@@ -499,7 +528,8 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
         }
 
         const double t_next = next < s->n_samples ? s->t_samples[next] : p->t_end;
-        const double Gmax = val(G0) * (1.0 + val(k.gamma) * s->L_max);
+        // the fastest face moves at |G0| (1 + gamma L_max), growing or dissolving
+        const double Gmax = std::fabs(val(G0)) * (1.0 + val(k.gamma) * s->L_max);
         const double cfl_limit = Gmax > 0.0 ? p->cfl * dL / Gmax : std::numeric_limits<double>::infinity();
         double dtv;
         const int kind = choose_dt(cfl_limit, p->dt_max, val(t), t_next, p->t_end, s->dt_replay, s->n_replay, step,
@@ -507,7 +537,7 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
         const bool hit = kind == DT_LAND;
         // the step as a function of the state and parameters, in the branch the values select
         R dt(dtv);
-        if (kind == DT_CFL) dt = with_value(p->cfl * dL / (G0 * (1.0 + k.gamma * s->L_max)), dtv);
+        if (kind == DT_CFL) dt = with_value(p->cfl * dL / (fabs(G0) * (1.0 + k.gamma * s->L_max)), dtv);
         if (kind == DT_LAND) dt = with_value(t_next - t, dtv);
         if (s->dt_log) s->dt_log[step] = dtv;
         if (s->G0_log) s->G0_log[step] = val(G0);
@@ -670,7 +700,11 @@ void mom_rhs(const MomSystem& sys, double t, const double* y, double* dy) {
         const double Sp = supersaturation_pos(y[4], solubility(sys.p, T));
         double G0, G2, B;
         rate_laws(sys.p->law, k, T, Sp, G0, G2, B);
-        // d/dt int L^k f = k int L^(k-1) G f (+ B for k = 0), G = G0 (1 + gamma L)
+        const double Gd = dissolution_rate(k, y[4], solubility(sys.p, T));
+        if (Gd < 0.0) G0 = Gd;
+        // d/dt int L^k f = k int L^(k-1) G f (+ B for k = 0), G = G0 (1 + gamma L);
+        // under dissolution this holds for k >= 1 (what leaves through L = 0 has
+        // zero size) and for mu_0 while no crystal reaches L = 0
         dy[0] = B;
         for (int m = 1; m <= 3; ++m) dy[m] = m * G0 * (y[m - 1] + k.gamma * y[m]);
         dy[4] = -sys.p->alpha * dy[3];

@@ -29,7 +29,14 @@
  * Per-simulation parameter row (REF_NPAR doubles):
  *   0 kg, 1 g, 2 kb, 3 b, 4 gamma [1/um], 5 kg2, 6 g2, 7 Eg [K], 8 Eb [K],
  *   9 T0, 10 T1, 11 t_ramp, 12 Eg2 [K] (the second axis' growth activation
- *   temperature of the Arrhenius law; App. A Eq. (A.2) has one per axis).
+ *   temperature of the Arrhenius law; App. A Eq. (A.2) has one per axis),
+ *   13 kd [m/s], 14 d: dissolution.  Where the solution is undersaturated
+ *   (C < Csat) the power and Arrhenius laws of a 1D simulation let crystals
+ *   shrink at G0 = -1e6 kd (1 - C/Csat)^d (um/s) with no nucleation; kd = 0
+ *   keeps them unchanged there.  With G0 < 0 the upwind cell of a face is the
+ *   one on its right: F = G (f_{i+1} - kappa/2 psi(f_{i+1} - f_i, f_{i+2} - f_{i+1})),
+ *   kappa = 1 or 1 - |G| dt/dL; crystals leave through L = 0 (a ghost of 0
+ *   left of it) and nothing enters through L_max (ghosts of 0 beyond it).
  */
 #ifndef PBE_ORACLE_H
 #define PBE_ORACLE_H
@@ -40,7 +47,7 @@
 extern "C" {
 #endif
 
-#define REF_NPAR 13
+#define REF_NPAR 15
 #define REF_NTAN 5          /* tangent directions: kg, g, kb, b, gamma */
 
 enum { REF_SCHEME_SSPRK3 = 0, REF_SCHEME_LW_TVD = 1 };

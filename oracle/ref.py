@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpbe_oracle.so")
 SOURCES = [os.path.join(HERE, "pbe_oracle.cpp")]
-NPAR = 13
+NPAR = 15
 NTAN = 5
 DT_DIFF, DT_FROZEN = 0, 1
 MLP_NC = 18

@@ -38,8 +38,8 @@ SOL_LINEAR = 0         # Csat = cs0 + cs1*T
 SOL_EXP = 1            # Csat = cs0*exp(cs1*T)   (App. A, Eq. A.1)
 
 # per-simulation parameter row (NPAR doubles)
-P_KG, P_G, P_KB, P_B, P_GAMMA, P_KG2, P_G2, P_EG, P_EB, P_T0, P_T1, P_TRAMP, P_EG2 = range(13)
-NPAR = 13
+P_KG, P_G, P_KB, P_B, P_GAMMA, P_KG2, P_G2, P_EG, P_EB, P_T0, P_T1, P_TRAMP, P_EG2, P_KD, P_D = range(15)
+NPAR = 15
 
 RHO_C_G_PER_UM3 = 1.11e-12          # crystal density, Table 1
 K_V = math.pi / 4.0                  # cylinder shape factor, Table 1
@@ -122,6 +122,75 @@ def gaussian_seed_2d(n1: int, n2: int, L1_max: float, L2_max: float,
     return np.ascontiguousarray(f, dtype=np.float64)
 
 
+# ---- seed distributions of SI S1.3: a sample PSSD from a normal or log-normal
+# distribution given its mean and (co)variance, scaled up to the crystallizer by
+# the seed mass: beta = m_seed / (rho_c k_v * mass moment of the sample)
+
+def lognormal_params(mean: float, sd: float):
+    """(mu, sigma) of ln L for a log-normal L with the given mean and standard deviation."""
+    s2 = math.log1p((sd / mean) ** 2)
+    return math.log(mean) - 0.5 * s2, math.sqrt(s2)
+
+
+def seed_sample_1d(kind: str, n: int, L_max: float, mean: float, sd: float) -> np.ndarray:
+    """Sample PSSD on n uniform cells of [0, L_max]: cell averages of a normal or log-normal
+    probability density with the given mean and standard deviation (CDF differences)."""
+    edges = np.linspace(0.0, L_max, n + 1)
+    if kind == "normal":
+        cdf = 0.5 * (1.0 + erf((edges - mean) / (sd * math.sqrt(2.0))))
+    elif kind == "lognormal":
+        mu, sig = lognormal_params(mean, sd)
+        with np.errstate(divide="ignore"):
+            z = (np.log(edges) - mu) / (sig * math.sqrt(2.0))
+        cdf = 0.5 * (1.0 + erf(z))
+    else:
+        raise ValueError(f"seed kind {kind!r}: 'normal' or 'lognormal'")
+    return np.maximum(np.diff(cdf) / (L_max / n), 0.0)
+
+
+def seed_sample_2d(kind: str, n1: int, n2: int, L1_max: float, L2_max: float, mean, cov) -> np.ndarray:
+    """Sample PSSD [n2][n1] (L1 fastest): a bivariate normal or log-normal probability density
+    at cell centres with mean vector `mean` and covariance matrix `cov` of (L1, L2)."""
+    m = np.asarray(mean, dtype=np.float64)
+    c = np.asarray(cov, dtype=np.float64)
+    d1, d2 = L1_max / n1, L2_max / n2
+    x = (np.arange(n1) + 0.5) * d1
+    y = (np.arange(n2) + 0.5) * d2
+    X, Y = np.meshgrid(x, y)
+    if kind == "normal":
+        mu, S, u, v, jac = m, c, X, Y, 1.0
+    elif kind == "lognormal":
+        # (ln L1, ln L2) is bivariate normal with Cov_ij = ln(1 + cov_ij / (m_i m_j))
+        S = np.log1p(c / np.outer(m, m))
+        mu = np.log(m) - 0.5 * np.diag(S)
+        u, v, jac = np.log(X), np.log(Y), 1.0 / (X * Y)
+    else:
+        raise ValueError(f"seed kind {kind!r}: 'normal' or 'lognormal'")
+    det = S[0, 0] * S[1, 1] - S[0, 1] * S[1, 0]
+    du, dv = u - mu[0], v - mu[1]
+    q = (S[1, 1] * du * du - 2.0 * S[0, 1] * du * dv + S[0, 0] * dv * dv) / det
+    f = np.exp(-0.5 * q) / (2.0 * math.pi * math.sqrt(det)) * jac
+    return np.ascontiguousarray(f, dtype=np.float64)
+
+
+def scale_to_seed_mass(f_sample: np.ndarray, m_seed: float, rho_kv: float, L_max, n_cells) -> np.ndarray:
+    """f0 = beta f_sample with beta = m_seed / (rho_c k_v * integral of the mass moment of the
+    sample): L^3 in one size coordinate (equant crystals), L1 L2^2 in two (SI S1.3); midpoint
+    rule at cell centres, as for the solver's moments."""
+    if np.ndim(L_max) == 0:
+        n = int(n_cells)
+        dL = float(L_max) / n
+        L = (np.arange(n) + 0.5) * dL
+        mass = float((L ** 3 * f_sample).sum() * dL)
+    else:
+        n1, n2 = int(n_cells[0]), int(n_cells[1])
+        d1, d2 = float(L_max[0]) / n1, float(L_max[1]) / n2
+        x = (np.arange(n1) + 0.5) * d1
+        y = (np.arange(n2) + 0.5) * d2
+        mass = float((x[None, :] * (y ** 2)[:, None] * f_sample.reshape(n2, n1)).sum() * d1 * d2)
+    return f_sample * (m_seed / (rho_kv * mass))
+
+
 @dataclass
 class Problem:
     """A batch of independent simulations plus the process settings they share.
@@ -197,12 +266,13 @@ class Problem:
 
 
 def _par_row(kg, g, kb, b, gamma=0.0, kg2=0.0, g2=0.0, Eg=0.0, Eb=0.0,
-             T0=T_HOT, T1=T_COLD, t_ramp=T_RAMP, Eg2=None) -> np.ndarray:
+             T0=T_HOT, T1=T_COLD, t_ramp=T_RAMP, Eg2=None, kd=0.0, d=1.0) -> np.ndarray:
     r = np.zeros(NPAR)
     r[P_KG], r[P_G], r[P_KB], r[P_B], r[P_GAMMA] = kg, g, kb, b, gamma
     r[P_KG2], r[P_G2], r[P_EG], r[P_EB] = kg2, g2, Eg, Eb
     r[P_T0], r[P_T1], r[P_TRAMP] = T0, T1, t_ramp
     r[P_EG2] = Eg if Eg2 is None else Eg2
+    r[P_KD], r[P_D] = kd, d
     return r
 
 
@@ -437,6 +507,43 @@ def cfl_limited(n_sims: int = 24, n_lo: int = 4, n_hi: int = 2048, t_end: float 
                    f0=np.concatenate(seeds), C0=np.array(C0), par=np.array(pars),
                    t_samples=np.array(ts, dtype=np.float64), t_end=t_end, dt_max=dt_max,
                    name=f"cfl-limited-{n_sims}x[{n_lo},{n_hi}]")
+
+
+def dissolution(n_sims: int = 32, n_lo: int = 4, n_hi: int = 2048, t_end: float = 3000.0, n_samples: int = 6,
+                seed_offset: int = 8, dt_max: float = 20.0, sizes=None, seed_kind: str = "lognormal") -> Problem:
+    """Heating runs that grow and then dissolve: a slightly supersaturated start at 20 degC
+    (C0 = Csat(20)(1 + U[0.02, 0.1])), heating to T1 ~ U[30, 45] degC over U[0.2, 0.6] t_end,
+    growth kg ~ log-U[1e-7, 5e-7] m/s with nucleation, dissolution kd ~ log-U[5e-7, 5e-6] m/s
+    with d ~ U[1, 1.5], gamma ~ U[0, 1e-3] 1/um.  Seeds (SI S1.3): `seed_kind` sample PSSDs with
+    mean U[80, 300] um and sd U[15, 60] um scaled to a seed mass alpha mu_3 = U[1e-3, 8e-3] g/g,
+    so that some runs dissolve every crystal and some only part.  Irregular sample times."""
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    ns_, pars, seeds, C0 = [], [], [], []
+    for i in range(n_sims):
+        kg = rng.log_uniform(1e-7, 5e-7)
+        g = rng.uniform_range(1.0, 2.0)
+        kb = rng.log_uniform(1e8, 1e10)
+        b = rng.uniform_range(1.0, 3.0)
+        gamma = rng.uniform_range(0.0, 1e-3)
+        kd = rng.log_uniform(5e-7, 5e-6)
+        d = rng.uniform_range(1.0, 1.5)
+        T1 = rng.uniform_range(30.0, 45.0)
+        t_ramp = rng.uniform_range(0.2, 0.6) * t_end
+        n = rng.randint(n_lo, n_hi) if sizes is None else int(sizes[i])
+        mean = rng.uniform_range(80.0, 300.0)
+        sd = rng.uniform_range(15.0, 60.0)
+        m_seed = rng.uniform_range(1e-3, 8e-3)
+        c_rel = rng.uniform_range(0.02, 0.1)
+        ns_.append(n)
+        pars.append(_par_row(kg, g, kb, b, gamma, T0=20.0, T1=T1, t_ramp=t_ramp, kd=kd, d=d))
+        sample = seed_sample_1d(seed_kind, n, 1000.0, mean, sd)
+        seeds.append(scale_to_seed_mass(sample, m_seed, ALPHA, 1000.0, n))
+        C0.append(csat_linear(20.0) * (1.0 + c_rel))
+    ts = sorted(rng.uniform_range(0.05, 0.95) * t_end for _ in range(n_samples - 1)) + [t_end]
+    return Problem(ndim=1, n_cells=np.array(ns_, dtype=np.int32), L_max=np.full(n_sims, 1000.0),
+                   f0=np.concatenate(seeds), C0=np.array(C0), par=np.array(pars),
+                   t_samples=np.array(ts, dtype=np.float64), t_end=t_end, dt_max=dt_max,
+                   name=f"dissolution-{n_sims}x[{n_lo},{n_hi}]")
 
 
 # ---- the paper's own 2D case (Table 1 and App. A, Table A.1)
