@@ -64,9 +64,14 @@ enum { PBE_FLAG_DEVICE_PTRS = 1,  /* output/cotangent pointers are device memory
 /* per-sim parameter row */
 /* kg [m/s], g, kb [#/(m^3 s)], b, gamma [1/um], kg2, g2 (2D second axis), Eg, Eb [K] (Arrhenius
  * law), T0, T1 [degC], t_ramp [s], Eg2 [K] (2D second axis, Arrhenius law: App. A Eq. (A.2) takes
- * one activation temperature per axis) */
+ * one activation temperature per axis), kd [m/s], d: dissolution.  In an undersaturated solution
+ * (C < Csat) the power and Arrhenius laws of a 1D simulation shrink the crystals at
+ * G0 = -1e6 kd (1 - C/Csat)^d um/s (the growth/dissolution rate of SI S1.1; this law mirrors the
+ * growth power law) with no nucleation; the upwind side of every face flips, crystals leave through
+ * L = 0 and nothing enters through L_max.  kd = 0 (the default) leaves them unchanged there.
+ * kd > 0 is refused (PBE_EUNSUPPORTED) by the 2D path, the other laws, and pbe_grad. */
 enum { PBE_P_KG = 0, PBE_P_G, PBE_P_KB, PBE_P_B, PBE_P_GAMMA, PBE_P_KG2, PBE_P_G2, PBE_P_EG, PBE_P_EB,
-       PBE_P_T0, PBE_P_T1, PBE_P_TRAMP, PBE_P_EG2, PBE_NPAR };
+       PBE_P_T0, PBE_P_T1, PBE_P_TRAMP, PBE_P_EG2, PBE_P_KD, PBE_P_D, PBE_NPAR };
 #define PBE_NGRAD 5   /* pbe_grad returns d/d(kg, g, kb, b, gamma) per sim */
 
 /* Learned closure (law PBE_LAW_MLP): the empirical hybrid model of Sec. 4.2,

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpbe.so")
 PBE_OK, PBE_EINVAL, PBE_ENOMEM, PBE_EDEVICE, PBE_ENONFINITE, PBE_ESTATE, PBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FLAG_DEVICE_PTRS, FLAG_RECORD_F, FLAG_AUTOTUNE, FLAG_RECORD_RATES = 1, 2, 4, 8
 SIM_OK, SIM_NONFINITE, SIM_OUTFLOW, SIM_FALLBACK, SIM_STEPCAP = 0, 1, 2, 4, 8
-NPAR = 13
+NPAR = 15
 NGRAD = 5
 
 # every entry point of include/pbe.h

@@ -19,7 +19,7 @@ using namespace dev;
 // `lane` the global lane 0..127 of the right-aligned layout.
 template <int K, int SCHEME, int CL, int W>
 __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
-    static_assert(W == 1 || CL == kClosureNone, "the closure kernels run one wavefront per simulation");
+    static_assert(W == 1 || CL == kClosureNone, "the closure and dissolution kernels run one wavefront per simulation");
     const int lane = W == 2 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     const int N = uniform(a.ncell[s]);
     const int64_t base = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
@@ -70,6 +70,8 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         Rates r;
         if constexpr (CL == kClosureNone) {
             r = rates_plain(p, q, C, t);
+        } else if constexpr (CL == kDissolve) {
+            r = rates_plain<true>(p, q, C, t);
         } else if constexpr (CL == kClosurePoly) {
             r = rates_poly<false>(p, q, C, t, a.poly + (int64_t)s * a.n_poly, a.n_poly, nullptr);
         } else {
@@ -109,7 +111,17 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         }
 
         const double cour = courant(dt, r.G0, inv_dL);
-        const double hN = fvm_step<K, SCHEME, W>(u, g, cour, ghost, pr);
+        double hN;
+        if constexpr (CL == kDissolve) {
+            if (cour < 0.0) {   // dissolving: nothing crosses L_max
+                fvm_step_dis<K, SCHEME>(u, g, cour);
+                hN = 0.0;
+            } else {
+                hN = fvm_step<K, SCHEME, W>(u, g, cour, ghost, pr);
+            }
+        } else {
+            hN = fvm_step<K, SCHEME, W>(u, g, cour, ghost, pr);
+        }
         out = fma(dt * r.G0, hN, out);
 
         // discrete solute balance, Eq. (9): C^{n+1} = C^n - alpha (mu3^{n+1} - mu3^n)
@@ -171,7 +183,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
 // closure kernels hold the 1-8 class at 4 (a few spills, but one wave per
 // simulation of a 4096-simulation batch fits the device at once) and the
 // 9-16 class at 2
-constexpr int fvm_waves_per_simd(int klo, int cl) {
+constexpr int fvm_waves_per_simd(int klo, int cl) {   // (kDissolve: as the plain laws)
     return (cl == kClosureBf16 || cl == kClosureFp64) ? (klo == 1 ? 4 : 2)
                                                       : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
 }
@@ -255,15 +267,14 @@ __global__ void k_reset_counter(int32_t* c, int n) {
 
 }  // namespace
 
-template <int SCHEME>
+template <int SCHEME, int N>
 static hipError_t launch_class(int cls, const Fvm1dArgs& a, int n_blocks, int begin, int count, int32_t* q,
                                hipStream_t st) {
-    constexpr int N = kClosureNone;
     switch (cls) {
         case 0: hipLaunchKernelGGL((k_fvm1d<SCHEME, 1, 8, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
         case 1: hipLaunchKernelGGL((k_fvm1d<SCHEME, 9, 16, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
         case 2:
-            if (a.pair_long)
+            if (N == kClosureNone && a.pair_long)
                 hipLaunchKernelGGL((k_fvm1d_pair<SCHEME>), dim3(n_blocks), dim3(128), 0, st, a, begin, count, q);
             else
                 hipLaunchKernelGGL((k_fvm1d<SCHEME, 17, 24, N>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
@@ -291,8 +302,14 @@ hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int beg
     if (a.closure == kClosurePoly) return launch_closure_class<kClosurePoly>(cls, a, n_blocks, begin, count, queue, st);
     if (a.closure == kClosureBf16) return launch_closure_class<kClosureBf16>(cls, a, n_blocks, begin, count, queue, st);
     if (a.closure == kClosureFp64) return launch_closure_class<kClosureFp64>(cls, a, n_blocks, begin, count, queue, st);
-    if (a.scheme == PBE_SCHEME_LW_TVD) return launch_class<PBE_SCHEME_LW_TVD>(cls, a, n_blocks, begin, count, queue, st);
-    return launch_class<PBE_SCHEME_SSPRK3>(cls, a, n_blocks, begin, count, queue, st);
+    if (a.closure == kDissolve) {
+        if (a.scheme == PBE_SCHEME_LW_TVD)
+            return launch_class<PBE_SCHEME_LW_TVD, kDissolve>(cls, a, n_blocks, begin, count, queue, st);
+        return launch_class<PBE_SCHEME_SSPRK3, kDissolve>(cls, a, n_blocks, begin, count, queue, st);
+    }
+    if (a.scheme == PBE_SCHEME_LW_TVD)
+        return launch_class<PBE_SCHEME_LW_TVD, kClosureNone>(cls, a, n_blocks, begin, count, queue, st);
+    return launch_class<PBE_SCHEME_SSPRK3, kClosureNone>(cls, a, n_blocks, begin, count, queue, st);
 }
 
 hipError_t launch_reset_counter(int32_t* counter, int n, hipStream_t st) {
@@ -308,8 +325,11 @@ static hipError_t occupancy(int cls, int pairs, int* per_cu) {
         case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 9, 16, CL>, 64, 0);
         case 2:
             if (pairs) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d_pair<R>, 128, 0);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 17, 24, kClosureNone>, 64, 0);
-        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 25, 32, kClosureNone>, 64, 0);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                per_cu, k_fvm1d<R, 17, 24, CL == kDissolve ? kDissolve : kClosureNone>, 64, 0);
+        default:
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                per_cu, k_fvm1d<R, 25, 32, CL == kDissolve ? kDissolve : kClosureNone>, 64, 0);
     }
 }
 
@@ -320,6 +340,7 @@ int fvm1d_class_resident_blocks(int cls, int closure, int pairs) {
     const hipError_t e = closure == kClosureBf16   ? occupancy<kClosureBf16>(cls, pairs, &per_cu)
                          : closure == kClosureFp64 ? occupancy<kClosureFp64>(cls, pairs, &per_cu)
                          : closure == kClosurePoly ? occupancy<kClosurePoly>(cls, pairs, &per_cu)
+                         : closure == kDissolve    ? occupancy<kDissolve>(cls, pairs, &per_cu)
                                                    : occupancy<kClosureNone>(cls, pairs, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);

@@ -122,6 +122,7 @@ struct Process {
 struct SimParams {
     double kg, g, kb, b, gamma, Eg, Eb, T0, T1, tr;
     double inv_tr;   // 1/tr (0 when tr = 0)
+    double kd, d;    // dissolution: G0 = -1e6 kd (-S)^d where S < 0
 };
 
 // (each value is made explicitly wave-uniform: loaded through a vector load,
@@ -133,6 +134,7 @@ __device__ __forceinline__ SimParams load_params(const double* P) {
     q.Eg = uniform(P[PBE_P_EG]); q.Eb = uniform(P[PBE_P_EB]); q.T0 = uniform(P[PBE_P_T0]);
     q.T1 = uniform(P[PBE_P_T1]); q.tr = uniform(P[PBE_P_TRAMP]);
     q.inv_tr = q.tr > 0.0 ? 1.0 / q.tr : 0.0;
+    q.kd = uniform(P[PBE_P_KD]); q.d = uniform(P[PBE_P_D]);
     return q;
 }
 
@@ -147,10 +149,14 @@ __device__ __forceinline__ double solubility(const Process& p, double T) {
 
 // Rates at the current concentration.  S = C/Csat - 1; growth G0 (um/s, at
 // L = 0) and nucleation B act only for S > 0.  S^g and S^b share one log.
+// DIS: below saturation the crystals dissolve at G0 = -1e6 kd (-S)^d (no
+// nucleation), the growth/dissolution rate of SI S1.1 in the form of the
+// growth power law.
 struct Rates {
     double G0, B, S, lnS, arrG, arrB;   // lnS and the Arrhenius factors are kept for the adjoint,
     double Sg, Sb;                      // and so are S^g and S^b
 };
+template <bool DIS = false>
 __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& q, double C, double t) {
     Rates r;
     const double T = temperature(q, t);
@@ -167,6 +173,8 @@ __device__ __forceinline__ Rates rates_plain(const Process& p, const SimParams& 
         r.Sb = exp64(q.b * r.lnS);
         r.G0 = 1e6 * q.kg * r.Sg * r.arrG;
         r.B = q.kb * r.Sb * r.arrB;
+    } else if (DIS && r.S < 0.0 && q.kd > 0.0) {
+        r.G0 = -1e6 * q.kd * exp64(q.d * log64(-r.S));
     }
     r.G0 = uniform(r.G0);
     r.B = uniform(r.B);
@@ -251,11 +259,11 @@ __device__ __forceinline__ Rates2 rates_2d(const Process& p, const SimParams& q,
     return r;
 }
 
-// Step size: CFL limit nu*dL/max_face G (G grows with L, so the max is at
+// Step size: CFL limit nu*dL/max_face |G| (|G| grows with L, so the max is at
 // L_max), capped by dt_max, landing exactly on the next sample time.
 __device__ __forceinline__ bool choose_dt(const Process& p, double G0, double gamma, double Lmax, double dL, double t,
                                           double t_next, double* dt) {
-    const double Gmax = G0 * (1.0 + gamma * Lmax);
+    const double Gmax = __builtin_fabs(G0) * (1.0 + gamma * Lmax);
     const double lim = Gmax > 0.0 ? div_fast(p.cfl * dL, Gmax) : __builtin_huge_val();
     const double d = fmin(lim, p.dt_max);
     const double rem = t_next - t;
@@ -434,6 +442,74 @@ __device__ __forceinline__ double fvm_step(double (&u)[K], const LaneGeom& g, do
     const double h1 = fvm_stage<K, SCHEME, W, LAG>(u, u0, g, c, ghost, 0.75, 0.25, false, pr);
     const double h2 = fvm_stage<K, SCHEME, W, LAG>(u, u0, g, c, ghost, 1.0 / 3.0, 2.0 / 3.0, false, pr);
     return fma(h0 + h1, 1.0 / 6.0, (2.0 / 3.0) * h2);
+}
+
+// ---------------------------------------------------------------- dissolution
+// With G0 < 0 the crystals shrink and every face takes its upwind value from
+// the cell on its right: the face right of cell i carries
+//   H = w (f_{i+1} - kappa/2 psi(f_{i+1} - f_i, f_{i+2} - f_{i+1})),
+// the mirror image of the growth face (psi is symmetric in its two slopes),
+// with kappa = 1 or 1 - |c| w.  Cells left of L = 0 (the pad slots and the
+// fill left of lane 0) are 0 in every stage: what crosses L = 0 has
+// dissolved.  Beyond L_max the density is 0, so nothing enters there.
+template <int SCHEME>
+__device__ __forceinline__ double face_value_dis(double a, double b, double up1, double w, double c) {
+    const double h = half_limited_slope(a, b);
+    if (SCHEME == PBE_SCHEME_LW_TVD) {
+        const double kappa = fma(c, w, 1.0);   // 1 - |c| w with c < 0
+        return w * fma(-kappa, h, up1);
+    }
+    return w * (up1 - h);
+}
+
+// One stage v = u + c (H_{i-1/2} - H_{i+1/2}) with c = dt G0/dL < 0, then
+// u <- first ? v : wa u0 + wb v, pad slots back to 0.  One wavefront per
+// simulation.  The face left of slot 0 is formed by each lane; the face right
+// of its last slot is the right neighbour's (0 past L_max).
+template <int K, int SCHEME>
+__device__ __forceinline__ void fvm_stage_dis(double (&u)[K], const double (&u0)[K], LaneGeom g, double c, double wa,
+                                              double wb, bool first) {
+    asm volatile("" : "+v"(g.xb));
+    const double uL = shift_from_left(u[K - 1], 0.0);                  // cell left of slot 0
+    const double uR = shift_from_right(u[0], 0.0);                     // cell right of slot K-1
+    const double u1 = K >= 2 ? u[K >= 2 ? 1 : 0] : uR;
+    const double Hfirst = face_value_dis<SCHEME>(u[0] - uL, u1 - u[0], u[0],
+                                                 fma(g.gdL, fmax(g.xb, 0.0), 1.0), c);
+    const double Hlast = shift_from_right(Hfirst, 0.0);
+    double Hprev = Hfirst;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double ui = u[k];
+        double H = Hlast;   // the last slot's right face is the right neighbour's first face
+        if (k + 1 < K) {
+            const double up1 = u[k + 1 < K ? k + 1 : 0];
+            const double up2 = (k + 2 < K) ? u[k + 2 < K ? k + 2 : 0] : uR;
+            H = face_value_dis<SCHEME>(up1 - ui, up2 - up1, up1, fma(g.gdL, fmax(g.xb + (double)(k + 1), 0.0), 1.0),
+                                       c);
+        }
+        const double v = ui + c * (Hprev - H);
+        const double nv = first ? v : wa * u0[k] + wb * v;
+        u[k] = k < g.npad ? 0.0 : nv;
+        Hprev = H;
+        if (k + 2 < K) asm volatile("" : "+v"(u[k + 2 < K ? k + 2 : 0]) : "v"(nv));
+    }
+}
+
+// Full dissolution step with frozen rates (SSP-RK3 or the one-step update).
+template <int K, int SCHEME>
+__device__ __forceinline__ void fvm_step_dis(double (&u)[K], const LaneGeom& g, double c) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = k < g.npad ? 0.0 : u[k];
+    double u0[K];
+    if (SCHEME == PBE_SCHEME_LW_TVD) {
+        fvm_stage_dis<K, SCHEME>(u, u0, g, c, 0.0, 1.0, true);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) u0[k] = u[k];
+    fvm_stage_dis<K, SCHEME>(u, u0, g, c, 0.0, 1.0, true);
+    fvm_stage_dis<K, SCHEME>(u, u0, g, c, 0.75, 0.25, false);
+    fvm_stage_dis<K, SCHEME>(u, u0, g, c, 1.0 / 3.0, 2.0 / 3.0, false);
 }
 
 // Load / store this lane's K cells of one simulation's packed array `row`

@@ -188,6 +188,12 @@ int validate(const pbe_problem* p) {
             return PBE_EINVAL;
         if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0)) return PBE_EINVAL;
         if (!(solubility(p, q[PBE_P_T0]) > 0.0) || !(solubility(p, q[PBE_P_T1]) > 0.0)) return PBE_EINVAL;
+        if (q[PBE_P_KD] < 0.0 || (q[PBE_P_KD] > 0.0 && !(q[PBE_P_D] > 0.0))) return PBE_EINVAL;
+        if (q[PBE_P_KD] > 0.0) {
+            // dissolution: the plain laws, forward only, one wavefront per simulation
+            if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return PBE_EUNSUPPORTED;
+            if (p->ckpt_every > 0) return PBE_EUNSUPPORTED;
+        }
         total += n;
     }
     for (int64_t i = 0; i < total; ++i)
@@ -237,6 +243,8 @@ int validate2d(const pbe_problem* p) {
             return PBE_EINVAL;
         if (p->law == PBE_LAW_ARRHENIUS && (q[PBE_P_EG] < 0.0 || q[PBE_P_EB] < 0.0 || q[PBE_P_EG2] < 0.0))
             return PBE_EINVAL;
+        if (q[PBE_P_KD] < 0.0) return PBE_EINVAL;
+        if (q[PBE_P_KD] > 0.0) return PBE_EUNSUPPORTED;   // the split solver grows only
         if (!(solubility(p, q[PBE_P_T0]) > 0.0) || !(solubility(p, q[PBE_P_T1]) > 0.0)) return PBE_EINVAL;
         total += (int64_t)n1 * n2;
     }
@@ -268,6 +276,8 @@ double step_bound(const pbe_problem* p, const double* q, int n, double Lmax, dou
     const double Smax = std::max(0.0, (C0 + p->alpha * mu3) / csat_min - 1.0);
     // (the Arrhenius factor exp(-Eg/(T+273.15)) is at most 1 for Eg >= 0)
     double G0max = 1e6 * q[PBE_P_KG] * std::pow(Smax, q[PBE_P_G]);
+    // dissolving: |G0| = 1e6 kd (-S)^d with 0 < -S < 1 (C > 0)
+    if (q[PBE_P_KD] > 0.0) G0max = std::max(G0max, 1e6 * q[PBE_P_KD]);
     if (p->law == PBE_LAW_MLP) G0max = std::max(G0max, std::exp(lnG0_max));
     if (p->law == PBE_LAW_POLY) {   // sum of a_j Smax^j with a_j >= 0
         G0max = 0.0;
@@ -926,6 +936,8 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     a.rate_log = (p->flags & PBE_FLAG_RECORD_RATES) ? m.get<double>((size_t)S * step_cap * 3) : nullptr;
     a.closure = kClosureNone;
     a.n_poly = 0;
+    for (int s = 0; s < S; ++s)
+        if (p->par[(size_t)s * PBE_NPAR + PBE_P_KD] > 0.0) a.closure = kDissolve;   // (validated: plain laws)
     if (p->law == PBE_LAW_POLY) {
         a.closure = kClosurePoly;
         a.n_poly = p->n_poly;
@@ -1111,6 +1123,10 @@ int pbe_set_par(pbe_handle* h, const double* par) {
             q[PBE_P_GAMMA] < 0.0 || q[PBE_P_TRAMP] < 0.0)
             return PBE_EINVAL;
         if (h->two_d && (q[PBE_P_KG2] < 0.0 || !(q[PBE_P_G2] > 0.0))) return PBE_EINVAL;
+        if (q[PBE_P_KD] < 0.0 || (q[PBE_P_KD] > 0.0 && !(q[PBE_P_D] > 0.0))) return PBE_EINVAL;
+        // dissolution needs the kernels chosen at create (a handle created with kd > 0)
+        if (q[PBE_P_KD] > 0.0 && (h->two_d || h->a.closure != kDissolve))
+            return h->two_d ? PBE_EUNSUPPORTED : PBE_ESTATE;
     }
     // The step cap (and with it the checkpoint count and the closure's gradient
     // rows) was sized at create from the kinetics then; new kinetics whose
@@ -1315,6 +1331,7 @@ namespace {
 int run_adjoint(pbe_handle* h, const double* gf, const double* gmom, const double* gC, double* gpar_out,
                 double* gmlp_out, double* gpoly_out) {
     if (h->p.ckpt_every <= 0 || !h->solved) return PBE_ESTATE;
+    if (h->a.closure == kDissolve) return PBE_EUNSUPPORTED;
     const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const size_t nf = (size_t)h->total * (h->a.record_f ? h->ns : 1);

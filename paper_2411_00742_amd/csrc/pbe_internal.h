@@ -32,7 +32,10 @@ struct ClosureDev {
 
 // rate-law variants of the 1D kernels: the plain laws, the learned closure
 // (bf16 or fp64 network) and the polynomial growth law
-enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2, kClosurePoly = 3 };
+// rate path of the kernels: the plain laws (growth only), the learned closure
+// (bf16 / fp64), the polynomial growth law, or the plain laws with dissolution
+// below saturation
+enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2, kClosurePoly = 3, kDissolve = 4 };
 constexpr int kMaxPoly = 1024;   // polynomial coefficients per simulation
 
 // Everything the 1D forward kernel reads or writes.  Device pointers only.

@@ -80,6 +80,10 @@ def _mutations():
     m("bad scheme", scheme=3)
     m("negative alpha", alpha=-1.0)
     m("solubility non-positive", cs0=-1.0)
+    par = base.par.copy(); par[1, W.P_KD] = -1e-7
+    m("negative kd", par=par)
+    par = base.par.copy(); par[0, W.P_KD] = 1e-7; par[0, W.P_D] = 0.0
+    m("zero dissolution exponent", par=par)
     return out
 
 
@@ -122,3 +126,13 @@ def test_gradient_options_rejected_on_host():
     assert _create_rc(two, ckpt_every=16) == pbe.PBE_EUNSUPPORTED
     assert _create_rc(two, record_f=True) == pbe.PBE_EUNSUPPORTED
     assert _create_rc(two, record_rates=True) == pbe.PBE_EUNSUPPORTED
+
+
+def test_dissolution_options_rejected_on_host():
+    """Dissolution runs the plain laws forward in 1D: no adjoint, no 2D, no other law."""
+    dis = W.dissolution(3, 100, 300)
+    assert _create_rc(dis, ckpt_every=16) == pbe.PBE_EUNSUPPORTED
+    assert _create_rc(dis.with_(law=W.LAW_POLY, poly=np.ones((3, 2)))) == pbe.PBE_EUNSUPPORTED
+    two = W.shape_2d(2, 16, 24, t_end=100.0, n_samples=2)
+    par = two.par.copy(); par[1, W.P_KD] = 1e-7
+    assert _create_rc(two.with_(par=par)) == pbe.PBE_EUNSUPPORTED
