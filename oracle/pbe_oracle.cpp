@@ -576,9 +576,10 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
 
 // ---------------------------------------------------------------------------
 // 2D solve: Godunov (Lie) splitting, a full L1 sweep over every row followed
-// by a full L2 sweep over every column, each one SSP-RK3 step (Sec. 2.1).
-// Nucleation at the corner L1 = L2 = 0 is split equally between the two
-// sweeps' inflow faces of the corner cell.
+// by a full L2 sweep over every column, each one SSP-RK3 step (Sec. 2.1); or
+// Strang splitting, L1 over dt/2, L2 over dt, L1 over dt/2.  Nucleation at the
+// corner L1 = L2 = 0 is split equally between the two axes' inflow faces of
+// the corner cell (under Strang the L1 share enters in two halves).
 // ---------------------------------------------------------------------------
 double moment2d(const std::vector<double>& f, int n1, int n2, double d1, double d2, int p, int q) {
     double m = 0.0;
@@ -629,25 +630,37 @@ int solve2d_impl(const ref_process* p, ref_sim2d* s) {
         const bool hit = choose_dt(p->cfl * lim, p->dt_max, t, t_next, p->t_end, nullptr, 0, step, &dt) == DT_LAND;
         if (s->dt_log) s->dt_log[step] = dt;
 
-        // sweep along L1: every row j is a 1D line of n1 cells
-        line.resize(n1);
-        for (int j = 0; j < n2; ++j) {
-            for (int i = 0; i < n1; ++i) line[i] = f[(size_t)j * n1 + i];
-            const double inflow = (j == 0 && G1 > 0.0) ? B / (2.0 * d2 * G1) : 0.0;
-            double o = 0.0;
-            advance_line(line, n1, d1, G1, 0.0, inflow, p->scheme, dt, o);
-            out += o * d2;
-            for (int i = 0; i < n1; ++i) f[(size_t)j * n1 + i] = line[i];
-        }
-        // sweep along L2: every column i is a 1D line of n2 cells
-        line.resize(n2);
-        for (int i = 0; i < n1; ++i) {
-            for (int j = 0; j < n2; ++j) line[j] = f[(size_t)j * n1 + i];
-            const double inflow = (i == 0 && G2 > 0.0) ? B / (2.0 * d1 * G2) : 0.0;
-            double o = 0.0;
-            advance_line(line, n2, d2, G2, 0.0, inflow, p->scheme, dt, o);
-            out += o * d1;
-            for (int j = 0; j < n2; ++j) f[(size_t)j * n1 + i] = line[j];
+        // sweep along L1 over a time h: every row j is a 1D line of n1 cells
+        auto sweep_rows = [&](double h) {
+            line.resize(n1);
+            for (int j = 0; j < n2; ++j) {
+                for (int i = 0; i < n1; ++i) line[i] = f[(size_t)j * n1 + i];
+                const double inflow = (j == 0 && G1 > 0.0) ? B / (2.0 * d2 * G1) : 0.0;
+                double o = 0.0;
+                advance_line(line, n1, d1, G1, 0.0, inflow, p->scheme, h, o);
+                out += o * d2;
+                for (int i = 0; i < n1; ++i) f[(size_t)j * n1 + i] = line[i];
+            }
+        };
+        // sweep along L2 over a time h: every column i is a 1D line of n2 cells
+        auto sweep_cols = [&](double h) {
+            line.resize(n2);
+            for (int i = 0; i < n1; ++i) {
+                for (int j = 0; j < n2; ++j) line[j] = f[(size_t)j * n1 + i];
+                const double inflow = (i == 0 && G2 > 0.0) ? B / (2.0 * d1 * G2) : 0.0;
+                double o = 0.0;
+                advance_line(line, n2, d2, G2, 0.0, inflow, p->scheme, h, o);
+                out += o * d1;
+                for (int j = 0; j < n2; ++j) f[(size_t)j * n1 + i] = line[j];
+            }
+        };
+        if (p->splitting == REF_SPLIT_STRANG) {
+            sweep_rows(0.5 * dt);
+            sweep_cols(dt);
+            sweep_rows(0.5 * dt);
+        } else {
+            sweep_rows(dt);
+            sweep_cols(dt);
         }
         // Eq. (9) with the volume moment mu_{1,2} = int L1 L2^2 f
         const double mu12 = moment2d(f, n1, n2, d1, d2, 1, 2);

@@ -80,12 +80,18 @@ enum { REF_SIM_OK = 0, REF_SIM_NONFINITE = 1, REF_SIM_OUTFLOW = 2, REF_SIM_FALLB
 #define REF_MLP_NBLOB (REF_MLP_NW + REF_MLP_NC)
 enum { REF_MLP_BF16 = 0, REF_MLP_FP64 = 1 };
 
+/* Dimensional splitting of the 2D step (Sec. 2.1): Godunov (Lie), a full L1
+ * sweep then a full L2 sweep; or Strang, an L1 sweep over half the step, the
+ * L2 sweep over the whole step, and another L1 sweep over the second half. */
+enum { REF_SPLIT_LIE = 0, REF_SPLIT_STRANG = 1 };
+
 typedef struct {
     int32_t law, scheme, sol_law, mlp_precision;
     double cs0, cs1;          /* Csat = cs0 + cs1*T (linear) or cs0*exp(cs1*T) */
     double alpha;             /* rho_c * k_v / rho_solvent, g/g per (um^3/m^3) */
     double cfl, dt_max, t_end;
     const float *mlp;         /* law == REF_LAW_MLP: closure blob [REF_MLP_NBLOB] */
+    int32_t splitting;        /* 2D: REF_SPLIT_LIE or REF_SPLIT_STRANG */
 } ref_process;
 
 /* One 1D simulation.  Inputs first, then optional outputs (NULL = skip). */

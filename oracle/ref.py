@@ -41,7 +41,7 @@ class Process(C.Structure):
     _fields_ = [("law", C.c_int32), ("scheme", C.c_int32), ("sol_law", C.c_int32), ("mlp_precision", C.c_int32),
                 ("cs0", C.c_double), ("cs1", C.c_double), ("alpha", C.c_double),
                 ("cfl", C.c_double), ("dt_max", C.c_double), ("t_end", C.c_double),
-                ("mlp", C.POINTER(C.c_float))]
+                ("mlp", C.POINTER(C.c_float)), ("splitting", C.c_int32)]
 
 
 class Sim1D(C.Structure):
@@ -114,7 +114,8 @@ def process_of(prob) -> Process:
         mlp = prob.mlp.ctypes.data_as(C.POINTER(C.c_float))
     return Process(law=prob.law, scheme=prob.scheme, sol_law=prob.sol_law,
                    mlp_precision=int(getattr(prob, "mlp_precision", 0)), cs0=prob.cs0, cs1=prob.cs1,
-                   alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max, t_end=prob.t_end, mlp=mlp)
+                   alpha=prob.alpha, cfl=prob.cfl, dt_max=prob.dt_max, t_end=prob.t_end, mlp=mlp,
+                   splitting=int(getattr(prob, "splitting", 0)))
 
 
 def phi_vanleer(theta: float) -> float:

@@ -34,6 +34,8 @@ LAW_POWER = 0          # G = kg*S^g (1 + gamma*L), B = kb*S^b
 LAW_ARRHENIUS = 1      # as above times exp(-E/(T+273.15)) (App. A, Eq. A.2 form)
 LAW_MLP = 2            # learned closure
 LAW_POLY = 3           # growth a_1 S + ... + a_k S^k (the polynomial law of Sec. 4.1)
+SPLIT_LIE = 0          # 2D: Godunov splitting, L1 sweep then L2 sweep (Sec. 2.1)
+SPLIT_STRANG = 1       # 2D: Strang splitting, L1 over dt/2, L2 over dt, L1 over dt/2
 SOL_LINEAR = 0         # Csat = cs0 + cs1*T
 SOL_EXP = 1            # Csat = cs0*exp(cs1*T)   (App. A, Eq. A.1)
 
@@ -221,6 +223,7 @@ class Problem:
     mlp: np.ndarray | None = None      # law == LAW_MLP: float32 closure blob [MLP_NBLOB]
     mlp_precision: int = 0             # MLP_BF16 or MLP_FP64
     poly: np.ndarray | None = None     # law == LAW_POLY: growth coefficients a_1..a_k per sim [S, k]
+    splitting: int = SPLIT_LIE         # 2D: SPLIT_LIE or SPLIT_STRANG
 
     @property
     def n_sims(self) -> int:
