@@ -59,7 +59,9 @@ enum { PBE_FLAG_DEVICE_PTRS = 1,  /* output/cotangent pointers are device memory
        PBE_FLAG_RECORD_F = 2,     /* record the number density at every sample time */
        PBE_FLAG_AUTOTUNE = 4,     /* 2D: pick the launch shape with pbe_tune at create (cached per
                                      process); 1D: PBE_EUNSUPPORTED (see pbe_tune) */
-       PBE_FLAG_RECORD_RATES = 8 };  /* 1D: record (dt, G0, B) of every step, read with pbe_rate_log */
+       PBE_FLAG_RECORD_RATES = 8,    /* 1D: record (dt, G0, B) of every step, read with pbe_rate_log */
+       PBE_FLAG_STRANG = 16 };       /* 2D: Strang splitting, L1 over dt/2, L2 over dt, L1 over dt/2,
+                                        instead of Godunov's L1 then L2 (Sec. 2.1); 1D: PBE_EUNSUPPORTED */
 
 /* per-sim parameter row */
 /* kg [m/s], g, kb [#/(m^3 s)], b, gamma [1/um], kg2, g2 (2D second axis), Eg, Eb [K] (Arrhenius

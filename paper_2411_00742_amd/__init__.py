@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpbe.so")
 
 PBE_OK, PBE_EINVAL, PBE_ENOMEM, PBE_EDEVICE, PBE_ENONFINITE, PBE_ESTATE, PBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-FLAG_DEVICE_PTRS, FLAG_RECORD_F, FLAG_AUTOTUNE, FLAG_RECORD_RATES = 1, 2, 4, 8
+FLAG_DEVICE_PTRS, FLAG_RECORD_F, FLAG_AUTOTUNE, FLAG_RECORD_RATES, FLAG_STRANG = 1, 2, 4, 8, 16
 SIM_OK, SIM_NONFINITE, SIM_OUTFLOW, SIM_FALLBACK, SIM_STEPCAP = 0, 1, 2, 4, 8
 NPAR = 15
 NGRAD = 5
@@ -122,7 +122,8 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
     if poly is not None:
         keep["poly"] = _arr(poly, np.float64)
     flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0) | \
-        (FLAG_AUTOTUNE if autotune else 0) | (FLAG_RECORD_RATES if record_rates else 0)
+        (FLAG_AUTOTUNE if autotune else 0) | (FLAG_RECORD_RATES if record_rates else 0) | \
+        (FLAG_STRANG if getattr(prob, "splitting", 0) == 1 else 0)
     st = PbeProblem(ndim=prob.ndim, n_sims=prob.n_sims,
                     n_cells=keep["n_cells"].ctypes.data_as(_ip), L_max=keep["L_max"].ctypes.data_as(_dp),
                     f0=keep["f0"].ctypes.data_as(_dp), C0=keep["C0"].ctypes.data_as(_dp),

@@ -1,7 +1,9 @@
 // 2D size-and-shape PBE (length L1 x width L2), Godunov dimensional splitting
 // (paper Sec. 2.1: the update of Eq. (8) applied along each length in turn,
-// L1 first), SSP-RK3 (or the one-step form of Eq. (8)) per sweep, FP64, many
-// simulations per launch (gfx950).
+// L1 first) or Strang splitting (L1 over dt/2, L2 over dt, L1 over dt/2: the
+// second L1 sweep runs on each finished row inside the same pass), SSP-RK3 (or
+// the one-step form of Eq. (8)) per sweep, FP64, many simulations per launch
+// (gfx950).
 //
 // One global step = two launches (captured in a graph by the host):
 //   k_step2d  both sweeps in one pass over the state.  A wavefront owns a tile
@@ -217,9 +219,20 @@ __device__ void finalize_sim(const Fvm2dArgs& a, int s, int init) {
 
 __global__ __launch_bounds__(64) void k_final2d(Fvm2dArgs a, int init) { finalize_sim(a, blockIdx.x, init); }
 
-template <int SCHEME>
+// Tile geometry: Godunov splitting sweeps L1 once, so a tile's first output
+// lane is the L1 halo's width in; Strang splitting sweeps L1 again on the
+// output rows, which takes a second halo on each side.
+template <int SCHEME, bool STRANG>
+struct Tile2d {
+    using H = Halo2d<SCHEME>;
+    static constexpr int lo = STRANG ? 2 * H::left : H::left;                   // first output lane
+    static constexpr int width = STRANG ? 64 - 2 * (H::left + H::right) : H::width;
+};
+
+template <int SCHEME, bool STRANG>
 __global__ __launch_bounds__(64) void k_step2d(Fvm2dArgs a, int parity) {
     using H = Halo2d<SCHEME>;
+    using TL = Tile2d<SCHEME, STRANG>;
     constexpr bool RK = SCHEME == PBE_SCHEME_SSPRK3;
     const int b = tile_of_block((int)blockIdx.x, (int)gridDim.x);
     if (b >= a.n_cb) return;
@@ -229,16 +242,18 @@ __global__ __launch_bounds__(64) void k_step2d(Fvm2dArgs a, int parity) {
     const int n1 = uniform(a.n1[s]), n2 = uniform(a.n2[s]);
     const int c0 = uniform(a.cb_col0[b]), r0 = uniform(a.cb_row0[b]);
     const int r1 = min(r0 + a.seg, n2);
-    const int col = c0 - H::left + lane;
+    const int col = c0 - TL::lo + lane;
     const bool left_ext = col < 0, right_ext = col >= n1;
     // a tile whose lanes all lie inside the domain needs no exterior masks
-    const bool interior = c0 - H::left >= 0 && c0 - H::left + 63 < n1;
-    const bool out_lane = lane >= H::left && lane < H::left + H::width && !right_ext;
+    const bool interior = c0 - TL::lo >= 0 && c0 - TL::lo + 63 < n1;
+    const bool out_lane = lane >= TL::lo && lane < TL::lo + TL::width && !right_ext;
     const int colc = min(max(col, 0), n1 - 1);
     const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
     const double* src = a.buf[parity] + o + colc;
     double* dst = a.buf[parity ^ 1] + o + colc;
-    const double c1 = uniform(a.c1[s]), c2 = uniform(a.c2[s]);
+    // Strang: each L1 sweep covers half the step (c1 * 0.5 = (dt/2) G1/dL1 exactly)
+    const double c1 = STRANG ? 0.5 * uniform(a.c1[s]) : uniform(a.c1[s]);
+    const double c2 = uniform(a.c2[s]);
     const double gh1 = uniform(a.gh1[s]);
     // column 0 receives half the corner source through its L2 = 0 face (the
     // L1 sweep's row 0 the other half, through its L1 = 0 face)
@@ -306,6 +321,18 @@ __global__ __launch_bounds__(64) void k_step2d(Fvm2dArgs a, int parity) {
             }
         }
         if (r >= r0 && r < r1) {
+            if constexpr (STRANG) {
+                // the second half-step L1 sweep, on the finished row r
+                double hN;
+                if (FAST || interior) {
+                    v = row_sweep_tile<SCHEME, false>(v, c1, 0.0, false, false, &hN);
+                } else {
+                    const double g1 = r == 0 ? gh1 : 0.0;
+                    v = row_sweep_tile<SCHEME, true>(left_ext ? g1 : (right_ext ? 0.0 : v), c1, g1, left_ext,
+                                                     right_ext, &hN);
+                    if (col == n1 - 1) hL1 += hN;
+                }
+            }
             if (out_lane) dst[(int64_t)r * n1] = v;
             const double f = out_lane ? v : 0.0;
             const double L2c = (r + 0.5) * d2;
@@ -358,16 +385,24 @@ __global__ void k_out2d(Fvm2dArgs a, double* f_out) {
 
 }  // namespace
 
-int step2d_tile_width(int scheme) {
-    return scheme == PBE_SCHEME_LW_TVD ? Halo2d<PBE_SCHEME_LW_TVD>::width : Halo2d<PBE_SCHEME_SSPRK3>::width;
+int step2d_tile_width(int scheme, int strang) {
+    if (strang)
+        return scheme == PBE_SCHEME_LW_TVD ? Tile2d<PBE_SCHEME_LW_TVD, true>::width
+                                           : Tile2d<PBE_SCHEME_SSPRK3, true>::width;
+    return scheme == PBE_SCHEME_LW_TVD ? Tile2d<PBE_SCHEME_LW_TVD, false>::width
+                                       : Tile2d<PBE_SCHEME_SSPRK3, false>::width;
 }
 
 hipError_t launch_step2d(const Fvm2dArgs& a, int parity, hipStream_t st) {
     const int blocks = (a.n_cb + 7) / 8 * 8;   // a multiple of 8 (see tile_of_block)
-    if (a.scheme == PBE_SCHEME_LW_TVD)
-        hipLaunchKernelGGL(k_step2d<PBE_SCHEME_LW_TVD>, dim3(blocks), dim3(64), 0, st, a, parity);
-    else
-        hipLaunchKernelGGL(k_step2d<PBE_SCHEME_SSPRK3>, dim3(blocks), dim3(64), 0, st, a, parity);
+    const dim3 g(blocks), w(64);
+    if (a.scheme == PBE_SCHEME_LW_TVD) {
+        if (a.strang) hipLaunchKernelGGL((k_step2d<PBE_SCHEME_LW_TVD, true>), g, w, 0, st, a, parity);
+        else hipLaunchKernelGGL((k_step2d<PBE_SCHEME_LW_TVD, false>), g, w, 0, st, a, parity);
+    } else {
+        if (a.strang) hipLaunchKernelGGL((k_step2d<PBE_SCHEME_SSPRK3, true>), g, w, 0, st, a, parity);
+        else hipLaunchKernelGGL((k_step2d<PBE_SCHEME_SSPRK3, false>), g, w, 0, st, a, parity);
+    }
     return hipGetLastError();
 }
 

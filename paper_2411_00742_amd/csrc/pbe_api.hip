@@ -171,9 +171,11 @@ int validate(const pbe_problem* p) {
         for (int s = 0; s < p->n_sims; ++s)
             if (p->n_cells[s] > kWave * 8 * kAdjClasses) return PBE_EUNSUPPORTED;
     }
-    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F | PBE_FLAG_AUTOTUNE | PBE_FLAG_RECORD_RATES))
+    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F | PBE_FLAG_AUTOTUNE | PBE_FLAG_RECORD_RATES |
+                     PBE_FLAG_STRANG))
         return PBE_EINVAL;
     if (p->flags & PBE_FLAG_AUTOTUNE) return PBE_EUNSUPPORTED;   // 1D tuning is switched off (see tune_handle)
+    if (p->flags & PBE_FLAG_STRANG) return PBE_EUNSUPPORTED;     // splitting is a 2D option
     int64_t total = 0;
     for (int s = 0; s < p->n_sims; ++s) {
         const int n = p->n_cells[s];
@@ -217,7 +219,8 @@ int validate_common(const pbe_problem* p) {
         if (q > 0 && !(tq > p->t_samples[q - 1])) return PBE_EINVAL;
     }
     if (p->ckpt_every < 0 || p->max_steps < 0) return PBE_EINVAL;
-    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F | PBE_FLAG_AUTOTUNE | PBE_FLAG_RECORD_RATES))
+    if (p->flags & ~(PBE_FLAG_DEVICE_PTRS | PBE_FLAG_RECORD_F | PBE_FLAG_AUTOTUNE | PBE_FLAG_RECORD_RATES |
+                     PBE_FLAG_STRANG))
         return PBE_EINVAL;
     return PBE_OK;
 }
@@ -433,7 +436,7 @@ double step_bound2d(const pbe_problem* p, int s) {
 // rows, sim by sim, row segments of one column strip consecutive
 int set_col_blocks(pbe_handle* h, int seg) {
     const int S = h->S;
-    const int tw = step2d_tile_width(h->p.scheme);
+    const int tw = step2d_tile_width(h->p.scheme, (h->p.flags & PBE_FLAG_STRANG) ? 1 : 0);
     std::vector<int32_t> cb[3], first(S + 1, 0);
     for (int s = 0; s < S; ++s) {
         first[s] = (int)cb[0].size();
@@ -486,6 +489,7 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
     Alloc& m = h->mem;
     Fvm2dArgs& a = h->a2;
     a.n_sims = S; a.n_samples = ns; a.law = p->law; a.sol_law = p->sol_law; a.scheme = p->scheme;
+    a.strang = (p->flags & PBE_FLAG_STRANG) ? 1 : 0;
     a.cs0 = p->cs0; a.cs1 = p->cs1; a.alpha = p->alpha; a.cfl = p->cfl; a.dt_max = p->dt_max; a.t_end = p->t_end;
     double* d_ts = m.get<double>(ns);
     int64_t* d_off = m.get<int64_t>(S + 1);
@@ -504,7 +508,7 @@ int create2d(pbe_handle* h, const pbe_problem* p) {
     a.c1 = m.get<double>(S); a.c2 = m.get<double>(S); a.gh1 = m.get<double>(S); a.gh2 = m.get<double>(S);
     a.dt = m.get<double>(S); a.hit = m.get<int32_t>(S);
     int64_t max_cb = 0;   // tiles at the shortest segment
-    const int tw = step2d_tile_width(p->scheme);
+    const int tw = step2d_tile_width(p->scheme, (p->flags & PBE_FLAG_STRANG) ? 1 : 0);
     for (int s = 0; s < S; ++s)
         max_cb += (int64_t)((n1v[s] + tw - 1) / tw) * ((n2v[s] + k2dSegMin - 1) / k2dSegMin);
     if (max_cb > (int64_t)std::numeric_limits<int32_t>::max() / 2) return PBE_EINVAL;
@@ -645,7 +649,7 @@ std::tuple<int, int, int, int, uint64_t> tune_key(const pbe_handle* h) {
     }
     mix((uint64_t)h->p.ckpt_every);
     mix((uint64_t)h->a.record_f);
-    return std::make_tuple(h->two_d ? 2 : 1, h->S, h->a.closure, h->p.scheme, x);
+    return std::make_tuple(h->two_d ? 2 : 1, h->S, h->a.closure, h->p.scheme + 2 * h->a2.strang, x);
 }
 
 void drop_graph(pbe_handle* h) {

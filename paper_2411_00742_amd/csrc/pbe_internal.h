@@ -106,7 +106,7 @@ constexpr int kClosureTape = 13;
 // L1 and then L2 (double buffered) with moment partials, and a per-sim finalize.
 struct Fvm2dArgs {
     int32_t n_sims, n_samples;
-    int32_t law, sol_law, scheme, pad0_;
+    int32_t law, sol_law, scheme, strang;   // strang: Strang splitting (else Godunov, L1 then L2)
     double cs0, cs1, alpha, cfl, dt_max, t_end;
     const double* t_samples;
     const int64_t* off;        // [S+1] cell offsets (sim s stored [n2][n1])
@@ -172,7 +172,7 @@ constexpr int kAdjClasses = 2;   // adjoint classes: cells per lane 1-8, 9-16 (g
 hipError_t launch_adj1d_class(int cls, const Adj1dArgs& A, int n_blocks, int begin, int count, int32_t* queue,
                               hipStream_t st);
 int adj1d_class_resident_blocks(int cls, int closure);
-int step2d_tile_width(int scheme);   // output columns of one 2D tile
+int step2d_tile_width(int scheme, int strang);   // output columns of one 2D tile
 hipError_t launch_step2d(const Fvm2dArgs& a, int parity, hipStream_t st);
 hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st);
 hipError_t launch_out2d(const Fvm2dArgs& a, double* f_out, hipStream_t st);

@@ -136,3 +136,8 @@ def test_dissolution_options_rejected_on_host():
     two = W.shape_2d(2, 16, 24, t_end=100.0, n_samples=2)
     par = two.par.copy(); par[1, W.P_KD] = 1e-7
     assert _create_rc(two.with_(par=par)) == pbe.PBE_EUNSUPPORTED
+
+
+def test_strang_is_a_2d_option():
+    one = W.batched(2, 200, 300, t_end=100.0, n_samples=2).with_(splitting=W.SPLIT_STRANG)
+    assert _create_rc(one) == pbe.PBE_EUNSUPPORTED

@@ -152,3 +152,40 @@ def test_paper_case_full_size_against_stored_oracle(torch_cuda):
         assert int(g["status"][0]) == case["status"]
         assert rel_each(g["mom"][0], np.array(case["mom"])) <= TOL
         assert rel_each(g["C"][0], np.array(case["C"])) <= TOL
+
+
+# --------------------------------------------------------------------------- Strang splitting
+@pytest.mark.parametrize("scheme,nu", [(W.SCHEME_SSPRK3, 0.5), (W.SCHEME_LW_TVD, 0.9)])
+def test_strang_tile_edges_and_both_schemes(torch_cuda, oracle, scheme, nu):
+    """Strang splitting (L1 over dt/2, L2 over dt, L1 over dt/2; the second L1 sweep runs on the
+    finished rows, so a tile owns 46 columns for SSP-RK3 and 58 for the one-step scheme): widths
+    straddling those, heights straddling the row segment, nucleation at the corner, rows wider
+    than 2048 cells."""
+    shapes = [(45, 20), (46, 129), (47, 127), (57, 128), (58, 130), (59, 64), (92, 65), (93, 33), (3000, 24),
+              (4, 4)]
+    p = problem2d(shapes, t_end=150.0).with_(scheme=scheme, cfl=nu, splitting=W.SPLIT_STRANG)
+    g = run_gpu(p)
+    compare(p, g, range(len(shapes)), oracle)
+
+
+def test_strang_outflow_and_cfl_limited(torch_cuda, oracle):
+    """Strang splitting with crystals leaving through both far edges and CFL-limited steps."""
+    shapes = [(300, 120), (520, 260), (700, 310)]
+    p = problem2d(shapes, t_end=300.0, S_boost=1.3)
+    seeds = [W.gaussian_seed_2d(n1, n2, 1200.0, 600.0, (1100.0, 540.0), (40.0, 30.0), 0.2, 1e9).ravel()
+             for (n1, n2) in shapes]
+    p = p.with_(f0=np.concatenate(seeds), dt_max=40.0, splitting=W.SPLIT_STRANG)
+    g = run_gpu(p)
+    for i in range(p.n_sims):
+        r = oracle.solve2d(p, i)
+        assert int(g["status"][i]) == r["status"], (i, g["status"][i], r["status"])
+        assert np.sum(r["dt"][: r["steps"]] < 40.0 * (1 - 1e-9)) > 0.5 * r["steps"]
+    compare(p, g, range(p.n_sims), oracle)
+
+
+def test_strang_paper_case(torch_cuda, oracle):
+    p = W.paper_2d(240, 120).with_(splitting=W.SPLIT_STRANG)
+    g = run_gpu(p)
+    compare(p, g, [0], oracle)
+    lie = run_gpu(W.paper_2d(240, 120))
+    assert not np.array_equal(lie["f"], g["f"])
