@@ -204,12 +204,13 @@ def closure_leg(steps: int):
                 closure_evals_per_s=rows / el, finite=finite)
 
 
-def fvm2d_leg(steps: int):
-    """2D length x width workload: 64 sims on n x n grids, n ~ U{256..1024}, Lie-split SSP-RK3."""
+def fvm2d_leg(steps: int, splitting: int = 0):
+    """2D length x width workload: 64 sims on n x n grids, n ~ U{256..1024}, SSP-RK3 per sweep,
+    Godunov (L1 then L2) or Strang (L1 over dt/2, L2 over dt, L1 over dt/2) splitting."""
     import torch
     import paper_2411_00742_amd as pbe
     from paper_2411_00742_amd import workloads as W
-    prob = W.shape_2d()
+    prob = W.shape_2d().with_(splitting=splitting)
     solver = pbe.Solver(prob)
     tuning = solver.tune(trial_steps=30)   # tile height chosen by the autotuner (pbe_tune)
     out = solver.solve()
@@ -227,6 +228,33 @@ def fvm2d_leg(steps: int):
                 cell_updates_per_solve=cu, ms_per_solve=1e3 * el,
                 hbm_frac_32B=32.0 * cu / el / (HBM_PEAK_GBS * 1e9),
                 tile_rows=tuning["seg_2d"], tuning_ms={"best": tuning["best_ms"], "default": tuning["default_ms"]})
+
+
+def dissolution_leg(steps: int):
+    """Growth then dissolution (heating runs, log-normal seeds scaled to a seed mass): 4096 sims,
+    N ~ U{200..2000}, 3000 s, SSP-RK3; the mirrored step runs whenever G0 < 0."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    from paper_2411_00742_amd import workloads as W
+    prob = W.dissolution(4096, 200, 2000)
+    solver = pbe.Solver(prob, record_rates=True)
+    out = solver.solve()
+    torch.cuda.synchronize()
+    st = out["steps"].cpu().numpy().astype(np.int64)
+    rates = solver.rate_log(int(st.max())).cpu().numpy()
+    neg = sum(int(np.sum(rates[s, :st[s], 1] < 0)) for s in range(prob.n_sims))
+    cu = int((st * prob.n_cells.astype(np.int64)).sum())
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.solve(out)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    solver.close()
+    longest = int(np.argmax(st * prob.n_cells))
+    return dict(value=cu / el, unit="cell-updates/s", n_sims=prob.n_sims, cell_updates_per_solve=cu,
+                ms_per_solve=1e3 * el, dissolving_step_fraction=neg / float(st.sum()),
+                steps_mean=float(st.mean()), steps_max=int(st.max()),
+                longest_sim=dict(cells=int(prob.n_cells[longest]), steps=int(st[longest])))
 
 
 def calibrate_copy(mib: int):
@@ -317,6 +345,7 @@ def main():
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-paper2d", action="store_true", help="skip the paper's 6000 x 3000 2D case")
     ap.add_argument("--no-pest", action="store_true", help="skip the parameter-estimation leg")
+    ap.add_argument("--no-next4", action="store_true", help="skip the Strang-splitting and dissolution legs")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first (pbe_tune)")
     ap.add_argument("--steps-closure", type=int, default=3)
     ap.add_argument("--steps-2d", type=int, default=2)
@@ -432,6 +461,12 @@ def main():
     if not args.no_2d:
         result["fvm2d"] = fvm2d_leg(args.steps_2d)
         log(f"[bench] 2D leg: {result['fvm2d']}")
+    if not args.no_2d and not args.no_next4:
+        result["fvm2d_strang"] = fvm2d_leg(args.steps_2d, splitting=1)
+        log(f"[bench] 2D Strang leg: {result['fvm2d_strang']}")
+    if not args.no_next4:
+        result["dissolution"] = dissolution_leg(args.steps_2d)
+        log(f"[bench] dissolution leg: {result['dissolution']}")
     if not args.no_paper2d:
         result["paper2d"] = paper2d_leg(args.steps_2d)
         log(f"[bench] paper 2D leg: {result['paper2d']}")

@@ -887,7 +887,11 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         const double* q = p->par + (size_t)s * PBE_NPAR;
         const double dL = p->L_max[s] / h->ncell[s];
         const double Sg = std::max(0.0, p->C0[s] / solubility(p, q[PBE_P_T1]) - 1.0) * 0.5;
-        const double G = 1e6 * q[PBE_P_KG] * std::pow(Sg, q[PBE_P_G]) * (1.0 + 0.5 * q[PBE_P_GAMMA] * p->L_max[s]);
+        double G = 1e6 * q[PBE_P_KG] * std::pow(Sg, q[PBE_P_G]) * (1.0 + 0.5 * q[PBE_P_GAMMA] * p->L_max[s]);
+        if (q[PBE_P_KD] > 0.0) {   // dissolution once heated past saturation: the faster of the two
+            const double Ud = std::max(0.0, 1.0 - p->C0[s] / solubility(p, q[PBE_P_T1])) * 0.5;
+            G = std::max(G, 1e6 * q[PBE_P_KD] * std::pow(Ud, q[PBE_P_D]) * (1.0 + 0.5 * q[PBE_P_GAMMA] * p->L_max[s]));
+        }
         const double dt = G > 0.0 ? std::min(p->dt_max, p->cfl * dL / G) : p->dt_max;
         cost[s] = (double)h->ncell[s] * (p->t_end / dt);
     }
