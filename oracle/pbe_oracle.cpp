@@ -112,6 +112,7 @@ struct Kinetics {
     double Eg, Eb, Eg2;
     double kd, d;           // dissolution (S < 0): G0 = -1e6 kd (-S)^d
     std::vector<R> poly;   // a_1..a_k of the polynomial growth law
+    std::vector<R> corr;   // in-the-loop correction weights (empty: none)
 };
 
 template <class R>
@@ -127,13 +128,21 @@ Kinetics<R> load_kinetics(const double* par) {
 // The kinetics of one 1D simulation: its parameter row and, for the polynomial
 // law, its coefficients (tangent direction: coefficient j moves along v[j]).
 template <class R>
-Kinetics<R> load_kinetics_sim(const ref_sim1d* s, const double* v = nullptr, int dir = -1) {
+Kinetics<R> load_kinetics_sim(const ref_sim1d* s, const double* v = nullptr, int dir = -1,
+                              const double* vc = nullptr) {
     Kinetics<R> k = load_kinetics<R>(s->par);
     if (s->poly && s->n_poly > 0) {
         k.poly.resize(s->n_poly);
         for (int j = 0; j < s->n_poly; ++j) {
             k.poly[j] = R(s->poly[j]);
             if (v && dir >= 0) set_tangent(k.poly[j], dir, v[j]);
+        }
+    }
+    if (s->corr) {   // correction weights (tangent 0 moves them along vc)
+        k.corr.resize(REF_CORR_NW);
+        for (int j = 0; j < REF_CORR_NW; ++j) {
+            k.corr[j] = R(s->corr[j]);
+            if (vc) set_tangent(k.corr[j], 0, vc[j]);
         }
     }
     return k;
@@ -417,6 +426,42 @@ void advance_line(std::vector<R>& f, int n, double dL, const R& G0, const R& gam
     out = out + dt * (F0 / 6.0 + F1 / 6.0 + (2.0 / 3.0) * F2);
 }
 
+// In-the-loop correction (Sec. 4.2, Fig. 5b), applied after a growth step: a
+// small network reads the four cells around each interior face, scaled by
+// their largest magnitude, and the face's Courant number, and returns a
+// correction flux; the corrected state is f_i + Y_{i-1/2} - Y_{i+1/2}.  The
+// layout of the weights and the exact form are stated in pbe_oracle.h.
+template <class R>
+void correct_line(std::vector<R>& f, int n, double dL, const R& G0, const R& gamma, const R& dt,
+                  const std::vector<R>& w) {
+    const int H = REF_CORR_H;
+    const int oW1 = 0, oB1 = 5 * H, oW2 = 6 * H, oB2 = 7 * H;
+    auto cell = [&](int i) { return (i < 0 || i >= n) ? R(0.0) : f[i]; };
+    std::vector<R> Y(n + 1, R(0.0));   // Y[j]: face between cells j-1 and j; j = 0 and j = n stay 0
+    for (int j = 1; j < n; ++j) {
+        const int i = j - 1;
+        R x[4] = {cell(i - 1), cell(i), cell(i + 1), cell(i + 2)};
+        R sigma(0.0);
+        for (int q = 0; q < 4; ++q) {
+            const R a = fabs(x[q]);
+            if (val(a) > val(sigma)) sigma = a;
+        }
+        if (!(val(sigma) > 0.0)) continue;
+        const R nu = dt * G0 * (1.0 + gamma * (j * dL)) / dL;
+        R in[5];
+        for (int q = 0; q < 4; ++q) in[q] = x[q] / sigma;
+        in[4] = nu;
+        R y = w[oB2];
+        for (int h = 0; h < H; ++h) {
+            R a = w[oB1 + h];
+            for (int q = 0; q < 5; ++q) a = a + w[oW1 + h * 5 + q] * in[q];
+            y = y + w[oW2 + h] * tanh(a);
+        }
+        Y[j] = sigma * nu * y;
+    }
+    for (int i = 0; i < n; ++i) f[i] = f[i] + (Y[i] - Y[i + 1]);
+}
+
 // Moment mu_k = sum_i L_i^k f_i dL with L_i the cell centre (SI Eq. (S5),
 // midpoint quadrature).
 template <class R>
@@ -547,6 +592,7 @@ int solve1d_impl(const ref_process* p, ref_sim1d* s, const Kinetics<R>& k, Tange
         // inflow ghost cells hold B/G0, so that G0 * ghost = B.
         const R inflow = val(G0) > 0.0 ? B / G0 : R(0.0);
         advance_line(f, n, dL, G0, k.gamma, inflow, p->scheme, dt, out);
+        if (!k.corr.empty() && val(G0) > 0.0) correct_line(f, n, dL, G0, k.gamma, dt, k.corr);
 
         // Discrete mass balance, Eq. (9), with the 1D volume moment mu_3.
         const R mu3 = moment1d(f, n, dL, 3);
@@ -981,6 +1027,38 @@ int ref_tangent1d_poly(const ref_process* p, ref_sim1d* s, int32_t dt_mode, cons
     if (!p || !s || s->n < 1 || p->law != REF_LAW_POLY || !s->poly || s->n_poly < 1 || !v) return -1;
     if (dt_mode != REF_DT_DIFF && dt_mode != REF_DT_FROZEN) return -1;
     Kinetics<D> k = load_kinetics_sim<D>(s, v, 0);
+    k.gamma.d[1] = 1.0;
+    std::vector<D> tf((size_t)s->n_samples * s->n), tm((size_t)s->n_samples * 4), tc(s->n_samples);
+    Tangents<D> tan;
+    tan.f_samples = dF ? &tf : nullptr;
+    tan.mom = &tm;
+    tan.C = &tc;
+    ref_sim1d s1 = *s;
+    std::vector<double> dts;
+    if (dt_mode == REF_DT_FROZEN) {
+        dts = primal_schedule(p, s, nullptr);
+        s1.dt_replay = dts.data();
+        s1.n_replay = (int)dts.size();
+        s1.max_steps = (int)dts.size();
+    }
+    solve1d_impl<D>(p, &s1, k, &tan);
+    for (int q = 0; q < s->n_samples; ++q)
+        for (int d = 0; d < 2; ++d) {
+            if (dC) dC[q * 2 + d] = tc[q].d[d];
+            for (int m = 0; m < 4; ++m)
+                if (dM) dM[(q * 4 + m) * 2 + d] = tm[q * 4 + m].d[d];
+            if (dF)
+                for (int i = 0; i < s->n; ++i) dF[((size_t)q * s->n + i) * 2 + d] = tf[(size_t)q * s->n + i].d[d];
+        }
+    return 0;
+}
+
+int ref_tangent1d_corr(const ref_process* p, ref_sim1d* s, int32_t dt_mode, const double* v, double* dF, double* dM,
+                       double* dC) {
+    typedef Dual<2> D;
+    if (!p || !s || s->n < 1 || !s->corr || !v || p->law == REF_LAW_MLP) return -1;
+    if (dt_mode != REF_DT_DIFF && dt_mode != REF_DT_FROZEN) return -1;
+    Kinetics<D> k = load_kinetics_sim<D>(s, nullptr, -1, v);
     k.gamma.d[1] = 1.0;
     std::vector<D> tf((size_t)s->n_samples * s->n), tm((size_t)s->n_samples * 4), tc(s->n_samples);
     Tangents<D> tan;

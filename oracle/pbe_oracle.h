@@ -119,7 +119,21 @@ typedef struct {
     double *G0_log, *B_log;   /* [max_steps] rates used in each step */
     int32_t *steps, *status;
     double *C_final, *t_final, *outflow;
+    const double *corr;       /* NULL, or the in-the-loop correction's REF_CORR_NW weights (below) */
 } ref_sim1d;
+
+/* In-the-loop correction (Sec. 4.2, Fig. 5b: a network in the time loop that
+ * offsets the discretisation error of each step).  After every growth step
+ * (G0 > 0) each interior face i+1/2 (0 <= i <= n-2) gets a correction flux
+ *   Y = sigma nu (W2 . tanh(W1 x + b1) + b2),
+ *   x = (f_{i-1}, f_i, f_{i+1}, f_{i+2}) / sigma and nu,
+ * with sigma = max |f_{i-1..i+2}| (Y = 0 where sigma = 0), cells outside the
+ * domain read as 0, and nu = dt G0 (1 + gamma L_face) / dL the face's Courant
+ * number; then f_i += Y_{i-1/2} - Y_{i+1/2}.  The faces at L = 0 and L_max are
+ * not corrected, so the number balance and every boundary flux stay those of
+ * the solver.  Weights: W1[8][5] b1[8] W2[8] b2, REF_CORR_NW doubles. */
+#define REF_CORR_H 8
+#define REF_CORR_NW 57
 
 /* One 2D simulation, f stored [n2][n1] with L1 contiguous. */
 typedef struct {
@@ -173,6 +187,12 @@ int ref_tangent1d_mlp(const ref_process *p, ref_sim1d *s, int32_t dt_mode, const
  * direction v[n_poly] (tangent 0) and along gamma (tangent 1), steps as
  * dt_mode says.  dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
 int ref_tangent1d_poly(const ref_process *p, ref_sim1d *s, int32_t dt_mode, const double *v, double *dF, double *dM,
+                       double *dC);
+
+/* Solve with the in-the-loop correction (s->corr set): forward-mode derivatives
+ * along the weight direction v[REF_CORR_NW] (tangent 0) and along gamma
+ * (tangent 1), steps as dt_mode says.  dF [n_samples][n][2], dM [n_samples][4][2], dC [n_samples][2]. */
+int ref_tangent1d_corr(const ref_process *p, ref_sim1d *s, int32_t dt_mode, const double *v, double *dF, double *dM,
                        double *dC);
 
 int ref_solve2d(const ref_process *p, ref_sim2d *s);

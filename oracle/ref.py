@@ -53,7 +53,7 @@ class Sim1D(C.Structure):
                 ("f_samples", _dp), ("mom", _dp), ("C", _dp), ("f_final", _dp), ("dt_log", _dp),
                 ("G0_log", _dp), ("B_log", _dp),
                 ("steps", _ip), ("status", _ip),
-                ("C_final", _dp), ("t_final", _dp), ("outflow", _dp)]
+                ("C_final", _dp), ("t_final", _dp), ("outflow", _dp), ("corr", _dp)]
 
 
 class Sim2D(C.Structure):
@@ -94,6 +94,7 @@ def lib():
         L.ref_mlp_vjp.argtypes = [_fp, C.c_int32, C.c_int32, _dp, _dp, _dp]
         L.ref_tangent1d_mlp.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp, _dp]
         L.ref_tangent1d_poly.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp, _dp]
+        L.ref_tangent1d_corr.argtypes = [C.POINTER(Process), C.POINTER(Sim1D), C.c_int32, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -150,6 +151,8 @@ class _Sim1DBuffers:
             assert self.G0r.shape == self.Br.shape
         poly = getattr(prob, "poly", None)
         self.poly = None if poly is None else np.ascontiguousarray(poly[s], dtype=np.float64)
+        corr = getattr(prob, "corr", None)
+        self.corr = None if corr is None else np.ascontiguousarray(corr[s], dtype=np.float64)
         self.f_samples = np.zeros((ns, n)) if record_f else None
         self.mom = np.zeros((ns, 4))
         self.C = np.zeros(ns)
@@ -177,7 +180,7 @@ class _Sim1DBuffers:
                             C=_ptr(self.C), f_final=_ptr(self.f_final), dt_log=_ptr(self.dt_log),
                             G0_log=_ptr(self.G0_log), B_log=_ptr(self.B_log),
                             steps=_ptr(self.steps), status=_ptr(self.status), C_final=_ptr(self.C_final),
-                            t_final=_ptr(self.t_final), outflow=_ptr(self.outflow))
+                            t_final=_ptr(self.t_final), outflow=_ptr(self.outflow), corr=_ptr(self.corr))
 
     def result(self) -> dict:
         st = int(self.steps[0])
@@ -390,6 +393,27 @@ def tangent1d_poly(prob, s: int, v, with_f: bool = True, max_steps: int | None =
                                   _ptr(dF), _ptr(dM), _ptr(dC))
     if rc != 0:
         raise RuntimeError(f"ref_tangent1d_poly failed ({rc})")
+    out = dict(dM=dM, dC=dC)
+    if with_f:
+        out["dF"] = dF
+    return out
+
+
+def tangent1d_corr(prob, s: int, v, with_f: bool = True, max_steps: int | None = None, frozen_dt: bool = False):
+    """In-the-loop correction: derivatives along the weight direction v (tangent 0) and gamma
+    (tangent 1).  Returns dict with dF [ns, n, 2] (if with_f), dM [ns, 4, 2], dC [ns, 2]."""
+    buf = _Sim1DBuffers(prob, s, False, max_steps, None, 0)
+    n, ns = int(prob.n_cells[s]), len(prob.t_samples)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert buf.corr is not None and v.shape == buf.corr.shape
+    dF = np.zeros((ns, n, 2)) if with_f else None
+    dM = np.zeros((ns, 4, 2))
+    dC = np.zeros((ns, 2))
+    p = process_of(prob)
+    rc = lib().ref_tangent1d_corr(C.byref(p), C.byref(buf.struct), DT_FROZEN if frozen_dt else DT_DIFF, _ptr(v),
+                                  _ptr(dF), _ptr(dM), _ptr(dC))
+    if rc != 0:
+        raise RuntimeError(f"ref_tangent1d_corr failed ({rc})")
     out = dict(dM=dM, dC=dC)
     if with_f:
         out["dF"] = dF

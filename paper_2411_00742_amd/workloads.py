@@ -34,6 +34,7 @@ LAW_POWER = 0          # G = kg*S^g (1 + gamma*L), B = kb*S^b
 LAW_ARRHENIUS = 1      # as above times exp(-E/(T+273.15)) (App. A, Eq. A.2 form)
 LAW_MLP = 2            # learned closure
 LAW_POLY = 3           # growth a_1 S + ... + a_k S^k (the polynomial law of Sec. 4.1)
+CORR_H, CORR_NW = 8, 57   # in-the-loop correction network: W1[8][5] b1[8] W2[8] b2
 SPLIT_LIE = 0          # 2D: Godunov splitting, L1 sweep then L2 sweep (Sec. 2.1)
 SPLIT_STRANG = 1       # 2D: Strang splitting, L1 over dt/2, L2 over dt, L1 over dt/2
 SOL_LINEAR = 0         # Csat = cs0 + cs1*T
@@ -224,6 +225,7 @@ class Problem:
     mlp_precision: int = 0             # MLP_BF16 or MLP_FP64
     poly: np.ndarray | None = None     # law == LAW_POLY: growth coefficients a_1..a_k per sim [S, k]
     splitting: int = SPLIT_LIE         # 2D: SPLIT_LIE or SPLIT_STRANG
+    corr: np.ndarray | None = None     # 1D: in-the-loop correction weights per sim [S, CORR_NW]
 
     @property
     def n_sims(self) -> int:
@@ -260,7 +262,8 @@ class Problem:
                        cfl=self.cfl, dt_max=self.dt_max, t_end=self.t_end,
                        name=self.name + "[subset]", extra=dict(self.extra),
                        mlp=None if self.mlp is None else self.mlp.copy(), mlp_precision=self.mlp_precision,
-                       poly=None if self.poly is None else self.poly[idx].copy())
+                       poly=None if self.poly is None else self.poly[idx].copy(), splitting=self.splitting,
+                       corr=None if self.corr is None else self.corr[idx].copy())
 
     def with_(self, **kw) -> "Problem":
         d = dict(self.__dict__)
@@ -547,6 +550,43 @@ def dissolution(n_sims: int = 32, n_lo: int = 4, n_hi: int = 2048, t_end: float 
                    f0=np.concatenate(seeds), C0=np.array(C0), par=np.array(pars),
                    t_samples=np.array(ts, dtype=np.float64), t_end=t_end, dt_max=dt_max,
                    name=f"dissolution-{n_sims}x[{n_lo},{n_hi}]")
+
+
+def inloop(n_sims: int = 64, n_coarse: int = 50, refine: int = 16, t_end: float = 1800.0, n_samples: int = 30,
+           seed_offset: int = 9, dt: float = 2.0):
+    """Coarse / fine pairs for the in-the-loop correction (Sec. 4.2, Fig. 5b): the same simulations
+    on n_coarse cells and on refine * n_coarse cells of [0, 1000] um, with one step size dt for both
+    (dt_max, far below the CFL limit of the fine grid), so that the coarse grid's error is the
+    spatial discretisation error the correction is meant to offset.  Growth kg ~ log-U[1e-7, 4e-7]
+    m/s, g ~ U[1, 2], nucleation kb ~ log-U[1e7, 1e9], gamma ~ U[0, 1e-3] 1/um, cooling 40 -> 20 degC
+    over U[0.5, 1] t_end, seeds of mean U[100, 250] um and sd U[15, 40] um (normal or log-normal)
+    scaled to alpha mu_3 = U[2e-3, 1e-2] g/g.  Returns (coarse, fine)."""
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    nf = n_coarse * refine
+    pars, fc, ff, C0 = [], [], [], []
+    for i in range(n_sims):
+        kg = rng.log_uniform(1e-7, 4e-7)
+        g = rng.uniform_range(1.0, 2.0)
+        kb = rng.log_uniform(1e7, 1e9)
+        b = rng.uniform_range(1.0, 3.0)
+        gamma = rng.uniform_range(0.0, 1e-3)
+        t_ramp = rng.uniform_range(0.5, 1.0) * t_end
+        mean, sd = rng.uniform_range(100.0, 250.0), rng.uniform_range(15.0, 40.0)
+        kind = "lognormal" if rng.uniform() < 0.5 else "normal"
+        m_seed = rng.uniform_range(2e-3, 1e-2)
+        pars.append(_par_row(kg, g, kb, b, gamma, t_ramp=t_ramp))
+        fine = scale_to_seed_mass(seed_sample_1d(kind, nf, 1000.0, mean, sd), m_seed, ALPHA, 1000.0, nf)
+        ff.append(fine)
+        fc.append(fine.reshape(n_coarse, refine).mean(axis=1))    # the same seed, cell-averaged
+        C0.append(csat_linear(T_HOT) * 1.02)
+    ts = uniform_samples(n_samples, t_end)
+    common = dict(ndim=1, L_max=np.full(n_sims, 1000.0), C0=np.array(C0), par=np.array(pars), t_samples=ts,
+                  t_end=t_end, dt_max=dt)
+    coarse = Problem(n_cells=np.full(n_sims, n_coarse, dtype=np.int32), f0=np.concatenate(fc),
+                     name=f"inloop-coarse-{n_sims}x{n_coarse}", **common)
+    fine_p = Problem(n_cells=np.full(n_sims, nf, dtype=np.int32), f0=np.concatenate(ff),
+                     name=f"inloop-fine-{n_sims}x{nf}", **common)
+    return coarse, fine_p
 
 
 # ---- the paper's own 2D case (Table 1 and App. A, Table A.1)
