@@ -121,8 +121,25 @@ typedef struct {
     int32_t n_poly;             /* law == PBE_LAW_POLY: coefficients per sim, k in [1, PBE_MAX_POLY] */
     const double *poly;         /* law == PBE_LAW_POLY: host [S][n_poly] a_1..a_k, finite and >= 0 (the
                                    paper's constraint); grids of up to 1024 cells, SSP-RK3 */
+    const double *corr;         /* NULL, or host [S][PBE_CORR_NW]: weights of the in-the-loop correction
+                                   (below), per sim; 1D grids of up to 512 cells (the coarse grids it
+                                   stands in for fine ones on), power or Arrhenius law without
+                                   dissolution, forward only (ckpt_every = 0) */
 } pbe_problem;
 #define PBE_MAX_POLY 1024
+
+/* In-the-loop correction (Sec. 4.2, Fig. 5b: a network inside the time loop
+ * that offsets the discretisation error of each step, so a coarse grid can
+ * stand in for a fine one).  After every growth step (G0 > 0) each interior
+ * face i+1/2 (0 <= i <= N-2) of a simulation gets the correction flux
+ *   Y = sigma nu (W2 . tanh(W1 x + b1) + b2),  x = (f_{i-1}, f_i, f_{i+1}, f_{i+2}) / sigma, nu,
+ * sigma = max |f_{i-1..i+2}| (Y = 0 where sigma = 0; cells outside the domain
+ * read 0), nu = dt G0 (1 + gamma L_face) / dL the face's Courant number; then
+ * f_i += Y_{i-1/2} - Y_{i+1/2}.  The faces at L = 0 and L_max are left alone,
+ * so the number balance and every boundary flux are the solver's.  Weights
+ * (FP64): W1[8][5] b1[8] W2[8] b2. */
+#define PBE_CORR_H 8
+#define PBE_CORR_NW 57
 
 /* Create a handle: validates `p`, deep-copies every input to device memory
  * (the caller may free its buffers on return), orders the sims for the
@@ -185,6 +202,14 @@ int pbe_grad(pbe_handle *h, const double *gf, const double *gmom, const double *
  * pointers, derived step budget) when the new law's step bound exceeds the
  * budget sized at create. */
 int pbe_set_poly(pbe_handle *h, const double *poly);
+
+/* Replace every sim's correction weights (a handle created with pbe_problem.corr)
+ * with corr[S][PBE_CORR_NW] (host, or device with PBE_FLAG_DEVICE_PTRS; host
+ * values are checked to be finite) and restart from the initial condition.
+ * Waits for the handle's queued work.  PBE_ESTATE for a handle without the
+ * correction.  Training loops perturb the weights of many copies of a
+ * simulation in one call (batched forward differences). */
+int pbe_set_corr(pbe_handle *h, const double *corr);
 
 /* pbe_grad for the polynomial growth law (Sec. 4.1: the gradient of the
  * estimation loss with respect to the law's coefficients): the same

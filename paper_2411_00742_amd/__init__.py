@@ -28,8 +28,9 @@ NGRAD = 5
 EXPORTS = ["pbe_create", "pbe_step", "pbe_reset", "pbe_solve", "pbe_fetch", "pbe_grad", "pbe_set_par",
            "pbe_set_mlp", "pbe_mlp_forward", "pbe_adam", "pbe_tune", "pbe_set_launch", "pbe_destroy", "pbe_strerror",
            "pbe_last_kernel_ms", "pbe_rate_log", "pbe_mlp_vjp", "pbe_mlp_vjp_noalloc", "pbe_set_poly",
-           "pbe_grad_poly"]
+           "pbe_grad_poly", "pbe_set_corr"]
 MLP_VJP_NOALLOC_MAX_ROWS = 4096
+CORR_H, CORR_NW = 8, 57
 MLP_NW, MLP_NC = 4546, 18
 MLP_BF16, MLP_FP64 = 0, 1
 
@@ -45,7 +46,7 @@ class PbeProblem(C.Structure):
                 ("cs0", C.c_double), ("cs1", C.c_double), ("alpha", C.c_double), ("cfl", C.c_double),
                 ("dt_max", C.c_double), ("t_end", C.c_double), ("t_samples", _dp),
                 ("ckpt_every", C.c_int32), ("max_steps", C.c_int32), ("flags", C.c_int32),
-                ("mlp_precision", C.c_int32), ("n_poly", C.c_int32), ("poly", _dp)]
+                ("mlp_precision", C.c_int32), ("n_poly", C.c_int32), ("poly", _dp), ("corr", _dp)]
 
 
 class PbeTuning(C.Structure):
@@ -93,6 +94,7 @@ def lib():
         L.pbe_mlp_vjp_noalloc.argtypes = [C.POINTER(C.c_float), C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.pbe_set_poly.argtypes = [vp, vp]
         L.pbe_grad_poly.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pbe_set_corr.argtypes = [vp, vp]
         for name in EXPORTS:
             if name not in ("pbe_destroy", "pbe_strerror"):
                 getattr(L, name).restype = C.c_int
@@ -121,6 +123,9 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
     poly = getattr(prob, "poly", None)
     if poly is not None:
         keep["poly"] = _arr(poly, np.float64)
+    corr = getattr(prob, "corr", None)
+    if corr is not None:
+        keep["corr"] = _arr(corr, np.float64)
     flags = (FLAG_DEVICE_PTRS if device_ptrs else 0) | (FLAG_RECORD_F if record_f else 0) | \
         (FLAG_AUTOTUNE if autotune else 0) | (FLAG_RECORD_RATES if record_rates else 0) | \
         (FLAG_STRANG if getattr(prob, "splitting", 0) == 1 else 0)
@@ -135,7 +140,8 @@ def make_problem_struct(prob, ckpt_every=0, record_f=False, device_ptrs=True, ma
                     ckpt_every=ckpt_every, max_steps=max_steps, flags=flags,
                     mlp_precision=int(getattr(prob, "mlp_precision", 0)),
                     n_poly=0 if poly is None else int(keep["poly"].shape[1]),
-                    poly=keep["poly"].ctypes.data_as(_dp) if "poly" in keep else None)
+                    poly=keep["poly"].ctypes.data_as(_dp) if "poly" in keep else None,
+                    corr=keep["corr"].ctypes.data_as(_dp) if "corr" in keep else None)
     return st, keep
 
 
@@ -229,6 +235,15 @@ class Solver:
         assert c.shape == (self.S, self.n_poly)
         _check(lib().pbe_set_poly(self._h, _ptr(c)), "pbe_set_poly")
         self._poly_keep = c
+
+    def set_corr(self, corr):
+        """New in-the-loop correction weights [S, CORR_NW] (device tensor or host array)."""
+        self.generation += 1
+        t = self.torch
+        c = t.as_tensor(corr, dtype=t.float64).to(self.device).contiguous()
+        assert c.shape == (self.S, CORR_NW)
+        _check(lib().pbe_set_corr(self._h, _ptr(c)), "pbe_set_corr")
+        self._corr_keep = c
 
     def grad_poly(self, gf=None, gmom=None, gC=None):
         """d<cotangents, outputs>/d(polynomial coefficients) per sim [S, n_poly], and the

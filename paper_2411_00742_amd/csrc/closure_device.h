@@ -268,5 +268,55 @@ __device__ __forceinline__ ClosureRates closure_rates(const ClosureDev& cd, cons
     return r;
 }
 
+// In-the-loop correction (Sec. 4.2, Fig. 5b), after a growth step with
+// Courant factor c = dt G0/dL > 0: each interior face i+1/2 (0 <= i <= N-2)
+// carries Y = sigma nu (W2 . tanh(W1 x + b1) + b2) with x the four cells
+// f_{i-1..i+2} over sigma = their largest magnitude (cells outside the domain,
+// including the pad slots, read 0) and nu = c (1 + gamma L_face); then
+// f_i += Y_{i-1/2} - Y_{i+1/2}.  The end faces carry nothing.  wl: the sim's
+// PBE_CORR_NW weights W1[8][5] b1[8] W2[8] b2, staged in LDS (every read is
+// a broadcast).  One wavefront per simulation.  The slots are evaluated one
+// after the other (each slot's window is tied to the previous slot's result),
+// which keeps the eight hidden units of one face live at a time.
+template <int K>
+__device__ __forceinline__ void correct_step(double (&u)[K], LaneGeom g, double c, int N, const double* wl) {
+    constexpr int H = PBE_CORR_H;
+    asm volatile("" : "+v"(g.xb));
+    const double uL = shift_from_left(u[K - 1], 0.0);                        // cell left of slot 0
+    const double uR = shift_from_right(u[0], 0.0);                           // cell right of slot K-1
+    const double uR2 = shift_from_right(K >= 2 ? u[K >= 2 ? 1 : 0] : uR, 0.0);   // two right of slot K-1
+    double Y[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double xc = g.xb + (double)k;   // cell index of slot k
+        double fm1 = (xc - 1.0 >= 0.0) ? (k >= 1 ? u[k >= 1 ? k - 1 : 0] : uL) : 0.0;
+        double f0 = u[k];
+        double fp1 = k + 1 < K ? u[k + 1 < K ? k + 1 : 0] : uR;
+        double fp2 = k + 2 < K ? u[k + 2 < K ? k + 2 : 0] : (k + 2 == K ? uR : uR2);
+        if (k > 0) asm volatile("" : "+v"(fm1), "+v"(f0), "+v"(fp1), "+v"(fp2) : "v"(Y[k > 0 ? k - 1 : 0]));
+        const double sigma = fmax(fmax(__builtin_fabs(fm1), __builtin_fabs(f0)),
+                                  fmax(__builtin_fabs(fp1), __builtin_fabs(fp2)));
+        const bool ok = xc >= 0.0 && xc <= (double)(N - 2) && sigma > 0.0;
+        const double inv = ok ? 1.0 / sigma : 0.0;
+        const double nu = c * fma(g.gdL, xc + 1.0, 1.0);
+        const double x0 = fm1 * inv, x1 = f0 * inv, x2 = fp1 * inv, x3 = fp2 * inv;
+        double y = wl[7 * H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            double a = wl[5 * H + h];
+            a = fma(wl[h * 5 + 0], x0, a);
+            a = fma(wl[h * 5 + 1], x1, a);
+            a = fma(wl[h * 5 + 2], x2, a);
+            a = fma(wl[h * 5 + 3], x3, a);
+            a = fma(wl[h * 5 + 4], nu, a);
+            y = fma(wl[6 * H + h], tanh64(a), y);
+        }
+        Y[k] = ok ? sigma * nu * y : 0.0;
+    }
+    const double Y_in = shift_from_left(Y[K - 1], 0.0);   // face left of slot 0
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] += (k == 0 ? Y_in : Y[k >= 1 ? k - 1 : 0]) - Y[k];
+}
+
 }  // namespace dev
 }  // namespace pbe

@@ -39,6 +39,16 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
     g.npad = min(max(pad - lane * K, 0), K);
     const int i0 = lane * K - pad;   // cell index of slot 0
 
+    // in-the-loop correction: the sim's weights, staged in LDS once per simulation
+    [[maybe_unused]] const double* corr_w = nullptr;
+    if constexpr (CL == kCorrect) {
+        __shared__ double wsh[PBE_CORR_NW];
+        __syncthreads();   // the previous simulation's reads are done
+        if (lane < PBE_CORR_NW) wsh[lane] = a.corr[(int64_t)s * PBE_CORR_NW + lane];
+        __syncthreads();
+        corr_w = wsh;
+    }
+
     double u[K];
     load_cells(u, (a.from_initial ? a.f0 : a.f) + base, i0, g.npad, 0.0);
 
@@ -72,6 +82,8 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             r = rates_plain(p, q, C, t);
         } else if constexpr (CL == kDissolve) {
             r = rates_plain<true>(p, q, C, t);
+        } else if constexpr (CL == kCorrect) {
+            r = rates_plain(p, q, C, t);
         } else if constexpr (CL == kClosurePoly) {
             r = rates_poly<false>(p, q, C, t, a.poly + (int64_t)s * a.n_poly, a.n_poly, nullptr);
         } else {
@@ -121,6 +133,9 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             }
         } else {
             hN = fvm_step<K, SCHEME, W>(u, g, cour, ghost, pr);
+            if constexpr (CL == kCorrect) {
+                if (cour > 0.0) correct_step<K>(u, g, cour, N, corr_w);
+            }
         }
         out = fma(dt * r.G0, hN, out);
 
@@ -184,6 +199,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
 // simulation of a 4096-simulation batch fits the device at once) and the
 // 9-16 class at 2
 constexpr int fvm_waves_per_simd(int klo, int cl) {   // (kDissolve: as the plain laws)
+    if (cl == kCorrect) return 2;   // the correction network's eight hidden units need the registers
     return (cl == kClosureBf16 || cl == kClosureFp64) ? (klo == 1 ? 4 : 2)
                                                       : klo == 1 ? 4 : klo == 9 ? 3 : klo == 17 ? 2 : 1;
 }
@@ -302,6 +318,16 @@ hipError_t launch_fvm1d_class(int cls, const Fvm1dArgs& a, int n_blocks, int beg
     if (a.closure == kClosurePoly) return launch_closure_class<kClosurePoly>(cls, a, n_blocks, begin, count, queue, st);
     if (a.closure == kClosureBf16) return launch_closure_class<kClosureBf16>(cls, a, n_blocks, begin, count, queue, st);
     if (a.closure == kClosureFp64) return launch_closure_class<kClosureFp64>(cls, a, n_blocks, begin, count, queue, st);
+    if (a.closure == kCorrect) {   // grids of up to 512 cells (the coarse grids it is meant for)
+        if (cls != 0) return hipErrorInvalidValue;
+        if (a.scheme == PBE_SCHEME_LW_TVD)
+            hipLaunchKernelGGL((k_fvm1d<PBE_SCHEME_LW_TVD, 1, 8, kCorrect>), dim3(n_blocks), dim3(64), 0, st, a,
+                               begin, count, queue);
+        else
+            hipLaunchKernelGGL((k_fvm1d<PBE_SCHEME_SSPRK3, 1, 8, kCorrect>), dim3(n_blocks), dim3(64), 0, st, a,
+                               begin, count, queue);
+        return hipGetLastError();
+    }
     if (a.closure == kDissolve) {
         if (a.scheme == PBE_SCHEME_LW_TVD)
             return launch_class<PBE_SCHEME_LW_TVD, kDissolve>(cls, a, n_blocks, begin, count, queue, st);
@@ -322,7 +348,9 @@ static hipError_t occupancy(int cls, int pairs, int* per_cu) {
     constexpr int R = PBE_SCHEME_SSPRK3;
     switch (cls) {
         case 0: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 1, 8, CL>, 64, 0);
-        case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d<R, 9, 16, CL>, 64, 0);
+        case 1:   // (the correction runs the first class only)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                per_cu, k_fvm1d<R, 9, 16, CL == kCorrect ? kClosureNone : CL>, 64, 0);
         case 2:
             if (pairs) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_fvm1d_pair<R>, 128, 0);
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -341,6 +369,7 @@ int fvm1d_class_resident_blocks(int cls, int closure, int pairs) {
                          : closure == kClosureFp64 ? occupancy<kClosureFp64>(cls, pairs, &per_cu)
                          : closure == kClosurePoly ? occupancy<kClosurePoly>(cls, pairs, &per_cu)
                          : closure == kDissolve    ? occupancy<kDissolve>(cls, pairs, &per_cu)
+                         : closure == kCorrect     ? occupancy<kCorrect>(cls, pairs, &per_cu)
                                                    : occupancy<kClosureNone>(cls, pairs, &per_cu);
     if (e != hipSuccess) return 0;
     return cus * (per_cu > 0 ? per_cu : 1);

@@ -105,6 +105,7 @@ struct pbe_handle {
     std::vector<double> par_host;          // 1D: the current parameter rows (host copy)
     double lnG0_max = 0.0;           // closure: clamp on the network's ln G0
     double* d_poly = nullptr;        // polynomial law: [S][n_poly] coefficients
+    double* d_corr = nullptr;        // in-the-loop correction: [S][PBE_CORR_NW] weights
     double* d_gpoly = nullptr;       // polynomial law: [S][n_poly] their gradient (ckpt_every > 0)
     std::vector<double> poly_host;   // host copy for re-deriving the step bound
     bool derived_cap = false;        // step_cap was derived from the step bound (max_steps == 0)
@@ -164,6 +165,17 @@ int validate(const pbe_problem* p) {
     if (p->law == PBE_LAW_MLP) {
         const int rc = validate_closure(p);
         if (rc != PBE_OK) return rc;
+    }
+    if (p->corr) {
+        // the in-the-loop correction: plain growth laws, forward only
+        for (int64_t i = 0; i < (int64_t)p->n_sims * PBE_CORR_NW; ++i)
+            if (!is_finite(p->corr[i])) return PBE_EINVAL;
+        if (p->law != PBE_LAW_POWER && p->law != PBE_LAW_ARRHENIUS) return PBE_EUNSUPPORTED;
+        if (p->ckpt_every > 0) return PBE_EUNSUPPORTED;
+        for (int s = 0; s < p->n_sims; ++s) {
+            if (p->par[(size_t)s * PBE_NPAR + PBE_P_KD] > 0.0) return PBE_EUNSUPPORTED;
+            if (p->n_cells[s] > kWave * 8) return PBE_EUNSUPPORTED;   // coarse grids: up to 512 cells
+        }
     }
     if (p->ckpt_every > 0) {
         // the adjoint covers the SSP-RK3 scheme on grids up to 64*16 cells
@@ -230,6 +242,7 @@ int validate2d(const pbe_problem* p) {
     if (rc != PBE_OK) return rc;
     // the split solver is forward only; its outputs are moments and final states
     if (p->ckpt_every != 0 || (p->flags & (PBE_FLAG_RECORD_F | PBE_FLAG_RECORD_RATES))) return PBE_EUNSUPPORTED;
+    if (p->corr) return PBE_EUNSUPPORTED;   // the in-the-loop correction is 1D
     int64_t total = 0;
     for (int s = 0; s < p->n_sims; ++s) {
         const int n1 = p->n_cells[2 * s], n2 = p->n_cells[2 * s + 1];
@@ -846,7 +859,7 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     if (!h) return PBE_ENOMEM;
     h->p = *p;
     h->p.n_cells = nullptr; h->p.L_max = nullptr; h->p.f0 = nullptr; h->p.C0 = nullptr;
-    h->p.par = nullptr; h->p.mlp = nullptr; h->p.t_samples = nullptr;
+    h->p.par = nullptr; h->p.mlp = nullptr; h->p.t_samples = nullptr; h->p.poly = nullptr; h->p.corr = nullptr;
     h->user = static_cast<hipStream_t>(hip_stream);
     h->S = p->n_sims;
     h->ns = p->n_samples;
@@ -946,6 +959,11 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
     a.n_poly = 0;
     for (int s = 0; s < S; ++s)
         if (p->par[(size_t)s * PBE_NPAR + PBE_P_KD] > 0.0) a.closure = kDissolve;   // (validated: plain laws)
+    if (p->corr) {
+        a.closure = kCorrect;
+        h->d_corr = m.get<double>((size_t)S * PBE_CORR_NW);
+        a.corr = h->d_corr;
+    }
     if (p->law == PBE_LAW_POLY) {
         a.closure = kClosurePoly;
         a.n_poly = p->n_poly;
@@ -988,6 +1006,9 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         return fail(h, PBE_EDEVICE);
     if (a.closure == kClosurePoly &&
         hipMemcpy(h->d_poly, p->poly, sizeof(double) * (size_t)S * p->n_poly, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(h, PBE_EDEVICE);
+    if (a.closure == kCorrect &&
+        hipMemcpy(h->d_corr, p->corr, sizeof(double) * (size_t)S * PBE_CORR_NW, hipMemcpyHostToDevice) != hipSuccess)
         return fail(h, PBE_EDEVICE);
     if (a.closure == kClosureBf16 || a.closure == kClosureFp64) {
         if (hipMemcpy(h->d_blob, p->mlp, sizeof(float) * (PBE_MLP_NW + PBE_MLP_NC), hipMemcpyHostToDevice) !=
@@ -1328,6 +1349,25 @@ int pbe_set_poly(pbe_handle* h, const double* poly) {
                           h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
     if (!dev) h->poly_host.assign(poly, poly + n);
+    h->fresh = true;
+    h->solved = false;
+    return PBE_OK;
+}
+
+int pbe_set_corr(pbe_handle* h, const double* corr) {
+    if (!h || !corr) return PBE_EINVAL;
+    if (h->two_d || h->a.closure != kCorrect) return PBE_ESTATE;
+    const bool dev = (h->p.flags & PBE_FLAG_DEVICE_PTRS) != 0;
+    const size_t n = (size_t)h->S * PBE_CORR_NW;
+    if (!dev)
+        for (size_t i = 0; i < n; ++i)
+            if (!is_finite(corr[i])) return PBE_EINVAL;
+    // queued work may still read the weights; a device source is ordered after the caller's stream
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (enter(h) != PBE_OK) return PBE_EDEVICE;
+    HIP_OK(hipMemcpyAsync(h->d_corr, corr, sizeof(double) * n, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
     h->fresh = true;
     h->solved = false;
     return PBE_OK;

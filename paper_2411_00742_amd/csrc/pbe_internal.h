@@ -33,9 +33,9 @@ struct ClosureDev {
 // rate-law variants of the 1D kernels: the plain laws, the learned closure
 // (bf16 or fp64 network) and the polynomial growth law
 // rate path of the kernels: the plain laws (growth only), the learned closure
-// (bf16 / fp64), the polynomial growth law, or the plain laws with dissolution
-// below saturation
-enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2, kClosurePoly = 3, kDissolve = 4 };
+// (bf16 / fp64), the polynomial growth law, the plain laws with dissolution
+// below saturation, or the plain laws with the in-the-loop correction
+enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2, kClosurePoly = 3, kDissolve = 4, kCorrect = 5 };
 constexpr int kMaxPoly = 1024;   // polynomial coefficients per simulation
 
 // Everything the 1D forward kernel reads or writes.  Device pointers only.
@@ -79,6 +79,7 @@ struct Fvm1dArgs {
     ClosureDev cd;             // closure == kClosureBf16 / kClosureFp64
     double* rate_log;          // [S][step_cap][3] (dt, G0, B) of every step, or null
     const double* poly;        // closure == kClosurePoly: [S][n_poly] growth coefficients a_1..a_k
+    const double* corr;        // closure == kCorrect: [S][PBE_CORR_NW] in-the-loop correction weights
     int32_t n_poly, pad1_;
 };
 
