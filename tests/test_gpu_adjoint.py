@@ -78,7 +78,7 @@ def small_estimation(n_sims, sizes, t_end=400.0):
 
 @pytest.mark.parametrize("record_f", [True, False])
 def test_adjoint_matches_oracle_tangent(torch_cuda, oracle, record_f):
-    sizes = [64, 100, 129, 300, 511, 512, 700, 1000, 1024]
+    sizes = [64, 100, 129, 300, 511, 512, 513, 645, 700, 1000, 1024]   # 513-1024: wave pairs, K = 5..8
     prob = small_estimation(len(sizes), sizes)
     o, g, (gf, gmom, gC) = gpu_solve_and_grad(prob, record_f, seed=11)
     assert np.all(o["status"] == 0)
