@@ -144,17 +144,19 @@ typedef struct {
 /* Create a handle: validates `p`, deep-copies every input to device memory
  * (the caller may free its buffers on return), orders the sims for the
  * persistent launch and records the launch graph.  `hip_stream` is the HIP
- * stream all work is ordered on (NULL = default stream).
+ * stream all work is ordered on (NULL = default stream).  The state starts at
+ * the initial condition of Sec. 2.1 Eqs. (3)-(7): the seed f0 and c0, at t = 0.
  * Errors: PBE_EINVAL (any field out of range), PBE_ENOMEM, PBE_EDEVICE. */
 int pbe_create(const pbe_problem *p, void *hip_stream, pbe_handle **out);
 
 /* Advance every unfinished simulation by at most n_steps time steps from its
- * current state (the initial condition after create/reset).  Samples falling
- * inside are recorded.  If n_active_out != NULL the call waits and stores the
- * number of sims that have not reached t_end. */
+ * current state (the initial condition after create/reset): n_steps turns of
+ * the loop of Sec. 2.2 Fig. 1 (rates, step size, PSSD update, moments, solute
+ * balance).  Samples falling inside are recorded.  If n_active_out != NULL the
+ * call waits and stores the number of sims that have not reached t_end. */
 int pbe_step(pbe_handle *h, int32_t n_steps, int32_t *n_active_out);
 
-/* Restart from the initial condition. */
+/* Restart from the initial condition (Sec. 2.1 Eqs. (3)-(7)). */
 int pbe_reset(pbe_handle *h);
 
 /* Solve every simulation from the initial condition to t_end (one graph launch)
@@ -184,6 +186,7 @@ int pbe_fetch(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
  * of C_out) - each may be NULL for zero - write
  *   gpar_out  [S][PBE_NGRAD] = d<cot, outputs>/d(kg, g, kb, b, gamma) per sim,
  *   gmlp_out  law == MLP: [PBE_MLP_NW] d<cot, outputs>/d(closure weights), summed over sims
+ *             (double, not float: the sum runs over every (sim, step) row, ~1e7 of them)
  *             (may be NULL); ignored for other laws.
  * Every step size is differentiated in the branch the forward solve took: a
  * CFL-limited step (SI Eq. (S3)) through G0 and gamma, a step landing on a
@@ -321,7 +324,8 @@ int pbe_set_launch(pbe_handle *h, const pbe_tuning *t);
  * PBE_EUNSUPPORTED for 2D handles; PBE_EINVAL for n_steps out of range. */
 int pbe_rate_log(pbe_handle *h, int32_t n_steps, double *out);
 
-/* Release all device memory of the handle.  NULL is a no-op. */
+/* Release all device memory of the handle.  NULL is a no-op.  (Resource
+ * management only; no passage of the paper corresponds.) */
 void pbe_destroy(pbe_handle *h);
 
 /* Static message for a pbe_status code. */
