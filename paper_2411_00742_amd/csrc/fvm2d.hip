@@ -105,7 +105,7 @@ __device__ __forceinline__ double col_feed(ColStage& st, double x, double c, dou
     return out;
 }
 
-constexpr int kColAhead = 8;   // row loads in flight per wave
+constexpr int kColAhead = 12;   // row loads in flight per wave
 
 // Block b -> tile: the hardware hands consecutive blocks to the 8 XCDs in
 // turn, so blocks b, b + 8, b + 16, ... share an XCD (and its L2).  They get
