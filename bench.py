@@ -82,10 +82,39 @@ def cpu_baseline(prob, stride: int, threads: int):
     res1, _ = ref.solve1d_batch(prob, one_idx, n_threads=1)
     el1 = time.time() - t1
     cells1 = sum(int(r["steps"]) * int(prob.n_cells[s]) for r, s in zip(res1, one_idx))
-    return dict(value=cells / el, unit="cell-updates/s", cores=int(used), kind="oracle",
-                sample=f"{len(idx)} of {prob.n_sims} sims (every {stride}th), full 3600 s horizon, "
-                       f"{cells:.3e} cell-updates in {el:.1f} s",
-                single_thread=dict(value=cells1 / el1, unit="cell-updates/s", sims=len(one_idx)))
+    out = dict(value=cells / el, unit="cell-updates/s", cores=int(used), kind="oracle",
+               sample=f"{len(idx)} of {prob.n_sims} sims (every {stride}th), full 3600 s horizon, "
+                      f"{cells:.3e} cell-updates in {el:.1f} s",
+               single_thread=dict(value=cells1 / el1, unit="cell-updates/s", sims=len(one_idx)))
+    out.update(cpu_baseline_2d_and_grad(threads))
+    return out
+
+
+def cpu_baseline_2d_and_grad(threads: int):
+    """The oracle on stated subsets of the 2D shape workload (16 of 64 sims, their first 30 steps)
+    and of the gradient workload (16 of 1024 sims, forward-mode tangents along the 5 parameters,
+    the oracle's gradient), on `threads` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import ref
+    from paper_2411_00742_amd import workloads as W
+    p2 = W.shape_2d()
+    idx2 = list(range(0, p2.n_sims, 4))
+    t0 = time.time()
+    res2, used2 = ref.solve2d_batch(p2, idx2, n_threads=threads, max_steps=30)
+    el2 = time.time() - t0
+    cells2 = sum(int(r["steps"]) * int(p2.n_cells[s][0]) * int(p2.n_cells[s][1]) for r, s in zip(res2, idx2))
+    pe = W.estimation()[0]
+    idxg = list(range(0, pe.n_sims, 64))
+    t1 = time.time()
+    with ThreadPoolExecutor(max_workers=threads) as ex:   # the oracle's C calls release the GIL
+        list(ex.map(lambda s: ref.tangent1d(pe, s, with_f=False), idxg))
+    elg = time.time() - t1
+    return dict(fvm2d=dict(value=cells2 / el2, unit="cell-updates/s", cores=int(used2),
+                           sample=f"{len(idx2)} of {p2.n_sims} sims (every 4th), first 30 steps, "
+                                  f"{cells2:.3e} cell-updates in {el2:.1f} s"),
+                gradient=dict(value=len(idxg) / elg, unit="per-sim gradients/s (forward-mode tangent, 5 params)",
+                              cores=threads, sample=f"{len(idxg)} of {pe.n_sims} sims (every 64th), full horizon, "
+                                                    f"{elg:.1f} s"))
 
 
 def gradient_leg(steps: int):
