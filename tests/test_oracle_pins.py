@@ -379,6 +379,37 @@ def test_2d_reduces_to_1d_lines(oracle, axis):
         assert r1["steps"] == r2["steps"]
 
 
+@pytest.mark.parametrize("axis", [1, 2])
+def test_2d_arrhenius_axes_reduce_to_1d_lines(oracle, axis):
+    """App. A Eq. (A.2) with one activation temperature per axis: with growth along one axis
+    only, every line along it evolves as a 1D Arrhenius solve with that axis' constants (a
+    mix-up of Eg and Eg2, or of the axes, changes the rate and fails)."""
+    n1, n2 = 40, 32
+    T = 25.0
+    Eg, Eg2 = 2000.0, 3000.0
+    kg1, kg2 = (4e-7 * np.exp(Eg / 298.15), 0.0) if axis == 1 else (0.0, 4e-7 * np.exp(Eg2 / 298.15))
+    par = W._par_row(kg1, 1.0, 0.0, 2.0, 0.0, kg2, 1.5, Eg=Eg, T0=T, T1=T, t_ramp=1.0, Eg2=Eg2)
+    f0 = W.gaussian_seed_2d(n1, n2, 1200.0, 600.0, (400.0, 250.0), (30.0, 30.0), 0.3, 1e9)
+    p2 = W.Problem(ndim=2, n_cells=np.array([[n1, n2]], dtype=np.int32), L_max=np.array([[1200.0, 600.0]]),
+                   f0=f0.ravel(), C0=np.array([W.csat_linear(T) * 1.4]), par=par[None, :],
+                   t_samples=W.uniform_samples(3, 600.0), t_end=600.0, alpha=0.0, law=W.LAW_ARRHENIUS)
+    r2 = oracle.solve2d(p2, 0)
+    f2 = r2["f_final"]
+    k = 11
+    line0 = f0[k, :] if axis == 1 else f0[:, k]
+    Lm = 1200.0 if axis == 1 else 600.0
+    kg, g, E = (kg1, 1.0, Eg) if axis == 1 else (kg2, 1.5, Eg2)
+    par1 = W._par_row(kg, g, 0.0, 2.0, 0.0, Eg=E, T0=T, T1=T, t_ramp=1.0)
+    p1 = W.Problem(ndim=1, n_cells=np.array([len(line0)], dtype=np.int32), L_max=np.array([Lm]), f0=line0.copy(),
+                   C0=p2.C0.copy(), par=par1[None, :], t_samples=p2.t_samples, t_end=p2.t_end, alpha=0.0,
+                   law=W.LAW_ARRHENIUS)
+    r1 = oracle.solve1d(p1, 0)
+    got = f2[k, :] if axis == 1 else f2[:, k]
+    assert r1["steps"] == r2["steps"]
+    np.testing.assert_allclose(got, r1["f_final"], rtol=0, atol=1e-13 * line0.max())
+    assert np.max(np.abs(got - line0)) > 1e-3 * line0.max()     # the line did move
+
+
 def test_2d_number_grows_by_corner_nucleation(oracle):
     p = shape_problem(40, 40, 3e-7, 2e-7, kb=6e8, t_end=900.0)
     r = oracle.solve2d(p, 0)
