@@ -201,6 +201,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     double* tapeC = A.tape_C + (int64_t)s * Kc;
     double* tapeT = A.tape_t + (int64_t)s * Kc;
     double* tapeR = A.tape_r + (int64_t)s * Kc * kClosureTape;
+    double* tapeS = A.tape_s + (int64_t)s * Kc * kStepTape;
     double* rows = A.rows + (int64_t)s * A.row_cap * 5;
     // polynomial law: its coefficients, and d/da_j accumulated in LDS after the
     // stage buffers (lane l owns the exponents j = l + 1 + 64 m, slot m * 64 + l)
@@ -258,7 +259,24 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             double dt;
             const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
             const double ghost = inflow_ghost(r.B, r.G0);
-            (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, courant(dt, r.G0, inv_dL), ghost);
+            const double cf = courant(dt, r.G0, inv_dL);
+            if constexpr (CL == kClosureNone) {
+                // the step's scalars as the reverse step uses them, so that it
+                // reads them (one step ahead) instead of forming them again
+                const double Tm = temperature(q, t);
+                const double Csat = solubility(p, Tm);
+                const double dCsat = p.sol_law == PBE_SOL_EXP ? p.cs1 * Csat : p.cs1;
+                const double iT = 1.0 / (Tm + 273.15);
+                const double v[kStepTape] = {r.G0, r.B, r.S, r.lnS, r.arrG, r.arrB, r.Sg, r.Sb, dt, hit ? 1.0 : 0.0,
+                                             ghost, cf, Csat, -(C / Csat) * dCsat / Csat,
+                                             (q.tr > 0.0 && t < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0, iT * iT};
+                if (lane == 0) {
+                    double* ts_ = tapeS + (int64_t)(m - m0) * kStepTape;
+#pragma unroll
+                    for (int j = 0; j < kStepTape; ++j) ts_[j] = v[j];
+                }
+            }
+            (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, cf, ghost);
             LaneGeom g2 = g;
             asm volatile("" : "+v"(g2.xb));
             const double mu3 = wave_sum(lane_moment3(u, g2)) * dL4;
@@ -273,18 +291,30 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         // (each lane reads back only the tape addresses it wrote itself)
 
         // ---- reverse walk over the segment
-        // taped scalars of the first reverse step; each step prefetches the next one's
-        double Cn = uniform(tapeC[m1 - 1 - m0]);
-        double tn = uniform(tapeT[m1 - 1 - m0]);
+        // taped scalars of the first reverse step; each step prefetches the
+        // next one's.  Plain laws read everything from the step's record (lane
+        // j < kStepTape holds scalar j, kept as loaded until the step reads it,
+        // so no step waits on a load it has just issued: with the wait counter
+        // in order, that wait would also cover the state load above it) and
+        // need neither C nor t.
+        constexpr bool REC = CL == kClosureNone;
+        double Cn = REC ? 0.0 : uniform(tapeC[m1 - 1 - m0]);
+        double tn = REC ? 0.0 : uniform(tapeT[m1 - 1 - m0]);
+        double recn = REC ? tapeS[(int64_t)(m1 - 1 - m0) * kStepTape + (lane & (kStepTape - 1))] : 0.0;
         for (int m = m1; m > m0; --m) {
             // state at m-1 from the tape: issued first, consumed after the rates
             double u0[K];
             load_cells(u0, tape + (int64_t)(m - 1 - m0) * N, i0, g.npad, 0.0);
             const double Cm = Cn;
             const double tm = tn;
+            const double rec = recn;
             if (m - 1 > m0) {
-                Cn = uniform(tapeC[m - 2 - m0]);
-                tn = uniform(tapeT[m - 2 - m0]);
+                if constexpr (REC) {
+                    recn = tapeS[(int64_t)(m - 2 - m0) * kStepTape + (lane & (kStepTape - 1))];
+                } else {
+                    Cn = uniform(tapeC[m - 2 - m0]);
+                    tn = uniform(tapeT[m - 2 - m0]);
+                }
             }
             // cotangents of the samples taken at state m
             while (qs >= 0 && qstep == m) {
@@ -311,11 +341,13 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             }
 
             // samples reached at tm (the forward's sample index at step m-1)
-            while (nx > 0 && t_lo > tm) {
-                --nx;
-                t_hi = t_lo;
-                t_lo = t_lo2;
-                t_lo2 = nx > 1 ? uniform(ts[nx - 2]) : -__builtin_huge_val();
+            if constexpr (!REC) {
+                while (nx > 0 && t_lo > tm) {
+                    --nx;
+                    t_hi = t_lo;
+                    t_lo = t_lo2;
+                    t_lo2 = nx > 1 ? uniform(ts[nx - 2]) : -__builtin_huge_val();
+                }
             }
             Rates r;
             bool fb = true;        // plain power law at this step
@@ -323,7 +355,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             double cz[3] = {0.0, 0.0, 0.0}, cj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, cmu2 = 0.0;
             PolyTerms pt{0.0, 0.0, 0.0};
             if constexpr (CL == kClosureNone) {
-                r = rates_plain(p, q, Cm, tm);
+                r.G0 = bcast(rec, 0); r.B = bcast(rec, 1); r.S = bcast(rec, 2); r.lnS = bcast(rec, 3);
+                r.arrG = bcast(rec, 4); r.arrB = bcast(rec, 5); r.Sg = bcast(rec, 6); r.Sb = bcast(rec, 7);
             } else if constexpr (CL == kClosurePoly) {
                 r = rates_poly<true>(p, q, Cm, tm, coef, a.n_poly, &pt);
             } else {
@@ -346,10 +379,18 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                     cmu2 = uniform(tr[12]);
                 }
             }
-            double dt;
-            const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_hi, &dt);
-            const double ghost = inflow_ghost(r.B, r.G0);
-            const double c = courant(dt, r.G0, inv_dL);
+            double dt, ghost, c;
+            bool hit;
+            if constexpr (CL == kClosureNone) {
+                dt = bcast(rec, 8);
+                hit = bcast(rec, 9) != 0.0;
+                ghost = bcast(rec, 10);
+                c = bcast(rec, 11);
+            } else {
+                hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, tm, t_hi, &dt);
+                ghost = inflow_ghost(r.B, r.G0);
+                c = courant(dt, r.G0, inv_dL);
+            }
 
             // stage input states u0, u1, u2 into this wave's LDS
             set_pad(u0, g, ghost);
@@ -425,13 +466,23 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 G0b -= dtb * dt / r.G0;
                 gams -= dtb * dt * Lmax / wmax;
             }
-            // temperature of the ramp at t^{m-1}, the solubility and its slope
-            const double Tm = temperature(q, tm);
-            const double Csat = solubility(p, Tm);
-            const double dCsat = p.sol_law == PBE_SOL_EXP ? p.cs1 * Csat : p.cs1;
-            const double dTdt = (q.tr > 0.0 && tm < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0;
-            // dS/dT = -(C/Csat) Csat'(T) / Csat
-            const double dSdT = -(Cm / Csat) * dCsat / Csat;
+            // temperature of the ramp at t^{m-1}, the solubility and its slope,
+            // dS/dT = -(C/Csat) Csat'(T) / Csat (plain laws: from the record)
+            double Csat, dTdt, dSdT, iT2;
+            if constexpr (CL == kClosureNone) {
+                Csat = bcast(rec, 12);
+                dSdT = bcast(rec, 13);
+                dTdt = bcast(rec, 14);
+                iT2 = bcast(rec, 15);
+            } else {
+                const double Tm = temperature(q, tm);
+                Csat = solubility(p, Tm);
+                const double dCsat = p.sol_law == PBE_SOL_EXP ? p.cs1 * Csat : p.cs1;
+                dTdt = (q.tr > 0.0 && tm < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0;
+                dSdT = -(Cm / Csat) * dCsat / Csat;
+                const double iT = 1.0 / (Tm + 273.15);
+                iT2 = iT * iT;
+            }
             double Tb = 0.0;
             if (!fb) {
                 // closure: ln G0 = a0 + s0 y0 (held at its bound when clamped),
@@ -464,8 +515,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 Tb = Sbar * dSdT;
                 if (CL == kClosureNone && p.law == PBE_LAW_ARRHENIUS) {
                     // exp(-E/(T + 273.15)) factors
-                    const double iT = 1.0 / (Tm + 273.15);
-                    Tb += (G0b * r.G0 * q.Eg + Bb * r.B * q.Eb) * (iT * iT);
+                    Tb += (G0b * r.G0 * q.Eg + Bb * r.B * q.Eb) * iT2;
                 }
                 if constexpr (CL == kClosurePoly) {
                     // dG0/da_j = S^j

@@ -86,6 +86,7 @@ struct pbe_handle {
     float* d_blob = nullptr;         // [PBE_MLP_NW + PBE_MLP_NC] current weights and constants
     void* d_pack = nullptr;          // packed operands (closure_pack_bytes)
     double* d_tapeR = nullptr;       // [S * ckpt_every * kClosureTape]
+    double* d_tapeS = nullptr;       // [S * ckpt_every * kStepTape]
     double* d_rows = nullptr;        // [S * row_cap * 5]
     double* d_partial = nullptr;     // [n_partial * PBE_MLP_NW]
     double* d_gmlp = nullptr;        // [PBE_MLP_NW]
@@ -950,6 +951,7 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
         h->d_tape = m.cells((size_t)h->total * p->ckpt_every);
         h->d_tapeC = m.get<double>((size_t)S * p->ckpt_every);
         h->d_tapeT = m.get<double>((size_t)S * p->ckpt_every);
+        h->d_tapeS = m.get<double>((size_t)S * p->ckpt_every * kStepTape);
         h->d_gf = m.cells((size_t)h->total * (a.record_f ? ns : 1));
         h->d_gmom = m.get<double>((size_t)S * ns * 4);
         h->d_gC = m.get<double>((size_t)S * ns);
@@ -1406,6 +1408,7 @@ int run_adjoint(pbe_handle* h, const double* gf, const double* gmom, const doubl
     A.tape_C = h->d_tapeC;
     A.tape_t = h->d_tapeT;
     A.tape_r = h->d_tapeR;
+    A.tape_s = h->d_tapeS;
     A.rows = h->d_rows;
     A.row_cap = h->row_cap;
     A.gpoly = h->d_gpoly;

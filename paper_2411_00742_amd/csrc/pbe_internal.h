@@ -94,6 +94,7 @@ struct Adj1dArgs {
     double* tape_C;            // [S * ckpt_every]
     double* tape_t;            // [S * ckpt_every]
     double* tape_r;            // [S * ckpt_every * kClosureTape] closure quantities of each taped step
+    double* tape_s;            // [S * ckpt_every * kStepTape] per-step scalars of the plain laws
     double* rows;              // [S * row_cap * 5] per-step (z0, z1, z2, ybar0, ybar1) for the weight gradient
     int32_t row_cap;           // rows per simulation (>= step_cap, multiple of 16)
     int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
@@ -102,6 +103,10 @@ struct Adj1dArgs {
 // per taped step: flags (1 = fallback, 2 = ln G0 clamped), G0, B, z0, z1, z2,
 // dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2
 constexpr int kClosureTape = 13;
+// per taped step of the plain laws, as the forward formed them: G0, B, S,
+// ln S, the two Arrhenius factors, S^g, S^b, dt, landed-on-a-sample flag,
+// inflow ghost, Courant factor, Csat(T), dS/dT, dT/dt, 1/(T + 273.15)^2
+constexpr int kStepTape = 16;
 
 // 2D Godunov-split solver: per global step one pass over tiles that sweeps
 // L1 and then L2 (double buffered) with moment partials, and a per-sim finalize.
