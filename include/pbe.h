@@ -170,7 +170,10 @@ int pbe_reset(pbe_handle *h);
  * Any output may be NULL.  With PBE_FLAG_DEVICE_PTRS outputs are device
  * pointers written stream-ordered and the call returns without waiting;
  * otherwise they are host pointers and the call blocks.
- * With ckpt_every > 0 the forward pass also stores checkpoints for pbe_grad. */
+ * With ckpt_every > 0 the forward pass also stores checkpoints for pbe_grad;
+ * under law == MLP it also evaluates the network's input Jacobian at every step
+ * and keeps it with the step's network inputs and rates (104 B per sim-step,
+ * sized by the step cap), so that pbe_grad does not evaluate the network again. */
 int pbe_solve(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
               int32_t *steps_out, int32_t *status_out);
 

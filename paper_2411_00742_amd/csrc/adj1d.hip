@@ -200,7 +200,10 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     double* tape = A.tape + base * Kc;
     double* tapeC = A.tape_C + (int64_t)s * Kc;
     double* tapeT = A.tape_t + (int64_t)s * Kc;
-    double* tapeR = A.tape_r + (int64_t)s * Kc * kClosureTape;
+    // learned closure: the forward taped each step's closure quantities
+    // (lane j < kClosureTape reads quantity j of a step)
+    const double* tapeR = is_net(CL) ? a.ck_r + (int64_t)s * a.step_cap * kClosureTape : nullptr;
+    const int rj = min(lane, kClosureTape - 1);
     double* tapeS = A.tape_s + (int64_t)s * Kc * kStepTape;
     double* rows = A.rows + (int64_t)s * A.row_cap * 5;
     // polynomial law: its coefficients, and d/da_j accumulated in LDS after the
@@ -224,6 +227,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         LaneGeom gm = g;
         asm volatile("" : "+v"(gm.xb));
         double mu3_old = wave_sum(lane_moment3(u, gm)) * dL4;
+        double crn = is_net(CL) ? tapeR[(int64_t)m0 * kClosureTape + rj] : 0.0;   // one step ahead
         for (int m = m0; m < m1; ++m) {
             store_cells(u, tape + (int64_t)(m - m0) * N, i0, g.npad);
             if (lane == 0) {
@@ -236,25 +240,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             } else if constexpr (CL == kClosurePoly) {
                 r = rates_poly<false>(p, q, C, t, coef, a.n_poly, nullptr);
             } else {
-                // closure with the forward tangents d/dz0, d/dz2; taped for the reverse walk
-                LaneGeom g2 = g;
-                asm volatile("" : "+v"(g2.xb));
-                const double mu2 = wave_sum(lane_moment2(u, g2)) * dL3;
-                const ClosureRates cr = closure_rates<true, CL>(a.cd, p, q, C, t, mu2);
-                r.G0 = cr.G0;
-                r.B = cr.B;
-                if (lane == 0) {
-                    double* tr = tapeR + (int64_t)(m - m0) * kClosureTape;
-                    tr[0] = (cr.fallback ? 1.0 : 0.0) + (cr.clamped ? 2.0 : 0.0);
-                    tr[1] = cr.G0; tr[2] = cr.B;
-                    tr[3] = cr.z[0]; tr[4] = cr.z[1]; tr[5] = cr.z[2];
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        tr[6 + 2 * i] = cr.dy[0][i];
-                        tr[7 + 2 * i] = cr.dy[1][i];
-                    }
-                    tr[12] = mu2;
-                }
+                // learned closure: the rates the forward took at this step
+                const double cr = crn;
+                if (m + 1 < m1) crn = tapeR[(int64_t)(m + 1) * kClosureTape + rj];
+                r.G0 = bcast(cr, 1);
+                r.B = bcast(cr, 2);
             }
             double dt;
             const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
@@ -301,6 +291,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         double Cn = REC ? 0.0 : uniform(tapeC[m1 - 1 - m0]);
         double tn = REC ? 0.0 : uniform(tapeT[m1 - 1 - m0]);
         double recn = REC ? tapeS[(int64_t)(m1 - 1 - m0) * kStepTape + (lane & (kStepTape - 1))] : 0.0;
+        // learned closure: the step's taped closure quantities, also one step ahead
+        double crecn = is_net(CL) ? tapeR[(int64_t)(m1 - 1) * kClosureTape + rj] : 0.0;
         for (int m = m1; m > m0; --m) {
             // state at m-1 from the tape: issued first, consumed after the rates
             double u0[K];
@@ -308,10 +300,12 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             const double Cm = Cn;
             const double tm = tn;
             const double rec = recn;
+            const double crec = crecn;
             if (m - 1 > m0) {
                 if constexpr (REC) {
                     recn = tapeS[(int64_t)(m - 2 - m0) * kStepTape + (lane & (kStepTape - 1))];
                 } else {
+                    if constexpr (is_net(CL)) crecn = tapeR[(int64_t)(m - 2) * kClosureTape + rj];
                     Cn = uniform(tapeC[m - 2 - m0]);
                     tn = uniform(tapeT[m - 2 - m0]);
                 }
@@ -360,8 +354,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             } else if constexpr (CL == kClosurePoly) {
                 r = rates_poly<true>(p, q, Cm, tm, coef, a.n_poly, &pt);
             } else {
-                const double* tr = tapeR + (int64_t)(m - 1 - m0) * kClosureTape;
-                const int flags = (int)uniform(tr[0]);
+                const int flags = (int)bcast(crec, 0);
                 fb = (flags & 1) != 0;
                 clamped = (flags & 2) != 0;
                 if (fb) {
@@ -369,14 +362,14 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                                      p.t_end};
                     r = rates_plain(pp, q, Cm, tm);
                 } else {
-                    r.G0 = uniform(tr[1]);
-                    r.B = uniform(tr[2]);
+                    r.G0 = bcast(crec, 1);
+                    r.B = bcast(crec, 2);
                     r.S = 0.0;
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) cz[i] = uniform(tr[3 + i]);
+                    for (int i = 0; i < 3; ++i) cz[i] = bcast(crec, 3 + i);
 #pragma unroll
-                    for (int i = 0; i < 6; ++i) cj[i] = uniform(tr[6 + i]);
-                    cmu2 = uniform(tr[12]);
+                    for (int i = 0; i < 6; ++i) cj[i] = bcast(crec, 6 + i);
+                    cmu2 = bcast(crec, 12);
                 }
             }
             double dt, ghost, c;

@@ -91,7 +91,27 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             LaneGeom g2 = g;
             asm volatile("" : "+v"(g2.xb));
             const double mu2 = wave_sum(lane_moment2(u, g2)) * dL3;
-            const ClosureRates cr = closure_rates<false, CL>(a.cd, p, q, C, t, mu2);
+            ClosureRates cr;
+            if (a.ck_r) {
+                // a solve that will be differentiated: also the network's input
+                // Jacobian (the tangent columns of the same matrix products),
+                // taped with the step's inputs and rates for the adjoint
+                cr = closure_rates<true, CL>(a.cd, p, q, C, t, mu2);
+                if (lane == 0) {
+                    double* tr = a.ck_r + ((int64_t)s * a.step_cap + step) * kClosureTape;
+                    tr[0] = (cr.fallback ? 1.0 : 0.0) + (cr.clamped ? 2.0 : 0.0);
+                    tr[1] = cr.G0; tr[2] = cr.B;
+                    tr[3] = cr.z[0]; tr[4] = cr.z[1]; tr[5] = cr.z[2];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        tr[6 + 2 * i] = cr.dy[0][i];
+                        tr[7 + 2 * i] = cr.dy[1][i];
+                    }
+                    tr[12] = mu2;
+                }
+            } else {
+                cr = closure_rates<false, CL>(a.cd, p, q, C, t, mu2);
+            }
             r.G0 = cr.G0;
             r.B = cr.B;
             r.S = cr.S;

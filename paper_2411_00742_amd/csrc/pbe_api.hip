@@ -85,7 +85,6 @@ struct pbe_handle {
     // learned closure
     float* d_blob = nullptr;         // [PBE_MLP_NW + PBE_MLP_NC] current weights and constants
     void* d_pack = nullptr;          // packed operands (closure_pack_bytes)
-    double* d_tapeR = nullptr;       // [S * ckpt_every * kClosureTape]
     double* d_tapeS = nullptr;       // [S * ckpt_every * kStepTape]
     double* d_rows = nullptr;        // [S * row_cap * 5]
     double* d_partial = nullptr;     // [n_partial * PBE_MLP_NW]
@@ -982,7 +981,8 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
             // one gradient row per (sim, step); rows are read in tiles of 16
             h->row_cap = (step_cap + 15) / 16 * 16;
             h->n_partial = 1024;
-            h->d_tapeR = m.get<double>((size_t)S * p->ckpt_every * kClosureTape);
+            // the closure quantities of every step, taped by the forward for the adjoint
+            a.ck_r = m.get<double>((size_t)S * step_cap * kClosureTape);
             h->d_rows = m.get<double>((size_t)S * h->row_cap * 5);
             h->d_partial = m.get<double>((size_t)h->n_partial * PBE_MLP_NW);
             h->d_gmlp = m.get<double>(PBE_MLP_NW);
@@ -1407,7 +1407,6 @@ int run_adjoint(pbe_handle* h, const double* gf, const double* gmom, const doubl
     A.tape = h->d_tape;
     A.tape_C = h->d_tapeC;
     A.tape_t = h->d_tapeT;
-    A.tape_r = h->d_tapeR;
     A.tape_s = h->d_tapeS;
     A.rows = h->d_rows;
     A.row_cap = h->row_cap;

@@ -38,6 +38,10 @@ struct ClosureDev {
 enum { kClosureNone = 0, kClosureBf16 = 1, kClosureFp64 = 2, kClosurePoly = 3, kDissolve = 4, kCorrect = 5 };
 constexpr int kMaxPoly = 1024;   // polynomial coefficients per simulation
 
+// per step of a learned-closure solve: flags (1 = fallback, 2 = ln G0 clamped),
+// G0, B, z0, z1, z2, dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2
+constexpr int kClosureTape = 13;
+
 // Everything the 1D forward kernel reads or writes.  Device pointers only.
 struct Fvm1dArgs {
     int32_t n_sims, n_samples;
@@ -81,6 +85,9 @@ struct Fvm1dArgs {
     const double* poly;        // closure == kClosurePoly: [S][n_poly] growth coefficients a_1..a_k
     const double* corr;        // closure == kCorrect: [S][PBE_CORR_NW] in-the-loop correction weights
     int32_t n_poly, pad1_;
+    // learned closure with checkpoints: [S][step_cap][kClosureTape] the closure
+    // quantities of every step, taped by the forward for the adjoint; else null
+    double* ck_r;
 };
 
 // Adjoint of the 1D solve (reverse sweep over checkpointed segments).
@@ -93,16 +100,12 @@ struct Adj1dArgs {
     double* tape;              // [sum N * ckpt_every] per-sim segment tape of states
     double* tape_C;            // [S * ckpt_every]
     double* tape_t;            // [S * ckpt_every]
-    double* tape_r;            // [S * ckpt_every * kClosureTape] closure quantities of each taped step
     double* tape_s;            // [S * ckpt_every * kStepTape] per-step scalars of the plain laws
     double* rows;              // [S * row_cap * 5] per-step (z0, z1, z2, ybar0, ybar1) for the weight gradient
     int32_t row_cap;           // rows per simulation (>= step_cap, multiple of 16)
     int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
     double* gpoly;             // polynomial law: [S][n_poly] d/d(a_1..a_k) output
 };
-// per taped step: flags (1 = fallback, 2 = ln G0 clamped), G0, B, z0, z1, z2,
-// dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2
-constexpr int kClosureTape = 13;
 // per taped step of the plain laws, as the forward formed them: G0, B, S,
 // ln S, the two Arrhenius factors, S^g, S^b, dt, landed-on-a-sample flag,
 // inflow ghost, Courant factor, Csat(T), dS/dT, dT/dt, 1/(T + 273.15)^2
