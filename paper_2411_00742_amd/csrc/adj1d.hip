@@ -214,6 +214,9 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     for (int m = 0; m < n_terms; ++m) ga[m * 64 + lane] = 0.0;
 
     const int n_seg = (n_total + Kc - 1) / Kc;
+    // plain laws and the learned closure: the recompute pass tapes a record of
+    // the step's scalars for the reverse step (the polynomial law forms them again)
+    constexpr bool REC = CL == kClosureNone || is_net(CL);
     for (int seg = n_seg - 1; seg >= 0; --seg) {
         const int m0 = seg * Kc;
         const int m1 = min(m0 + Kc, n_total);
@@ -240,17 +243,25 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             } else if constexpr (CL == kClosurePoly) {
                 r = rates_poly<false>(p, q, C, t, coef, a.n_poly, nullptr);
             } else {
-                // learned closure: the rates the forward took at this step
+                // learned closure: the rates the forward took at this step (the
+                // plain power law where the network's box excluded the state)
                 const double cr = crn;
                 if (m + 1 < m1) crn = tapeR[(int64_t)(m + 1) * kClosureTape + rj];
-                r.G0 = bcast(cr, 1);
-                r.B = bcast(cr, 2);
+                if ((int)bcast(cr, 0) & 1) {
+                    const Process pp{PBE_LAW_POWER, p.scheme, p.sol_law, p.cs0, p.cs1, p.alpha, p.cfl, p.dt_max,
+                                     p.t_end};
+                    r = rates_plain(pp, q, C, t);
+                } else {
+                    r.G0 = bcast(cr, 1);
+                    r.B = bcast(cr, 2);
+                    r.S = 0.0; r.lnS = 0.0; r.arrG = 1.0; r.arrB = 1.0; r.Sg = 0.0; r.Sb = 0.0;
+                }
             }
             double dt;
             const bool hit = choose_dt(p, r.G0, q.gamma, Lmax, dL, t, t_next, &dt);
             const double ghost = inflow_ghost(r.B, r.G0);
             const double cf = courant(dt, r.G0, inv_dL);
-            if constexpr (CL == kClosureNone) {
+            if constexpr (REC) {
                 // the step's scalars as the reverse step uses them, so that it
                 // reads them (one step ahead) instead of forming them again
                 const double Tm = temperature(q, t);
@@ -282,12 +293,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
 
         // ---- reverse walk over the segment
         // taped scalars of the first reverse step; each step prefetches the
-        // next one's.  Plain laws read everything from the step's record (lane
-        // j < kStepTape holds scalar j, kept as loaded until the step reads it,
-        // so no step waits on a load it has just issued: with the wait counter
-        // in order, that wait would also cover the state load above it) and
-        // need neither C nor t.
-        constexpr bool REC = CL == kClosureNone;
+        // next one's.  With a record (plain laws, learned closure) the step
+        // reads everything from it (lane j < kStepTape holds scalar j, kept as
+        // loaded until the step reads it, so no step waits on a load it has
+        // just issued: with the wait counter in order, that wait would also
+        // cover the state load above it) and needs neither C nor t.
         double Cn = REC ? 0.0 : uniform(tapeC[m1 - 1 - m0]);
         double tn = REC ? 0.0 : uniform(tapeT[m1 - 1 - m0]);
         double recn = REC ? tapeS[(int64_t)(m1 - 1 - m0) * kStepTape + (lane & (kStepTape - 1))] : 0.0;
@@ -304,8 +314,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             if (m - 1 > m0) {
                 if constexpr (REC) {
                     recn = tapeS[(int64_t)(m - 2 - m0) * kStepTape + (lane & (kStepTape - 1))];
-                } else {
                     if constexpr (is_net(CL)) crecn = tapeR[(int64_t)(m - 2) * kClosureTape + rj];
+                } else {
                     Cn = uniform(tapeC[m - 2 - m0]);
                     tn = uniform(tapeT[m - 2 - m0]);
                 }
@@ -354,17 +364,13 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             } else if constexpr (CL == kClosurePoly) {
                 r = rates_poly<true>(p, q, Cm, tm, coef, a.n_poly, &pt);
             } else {
+                // the rates from the record (the power law's where the network fell back)
                 const int flags = (int)bcast(crec, 0);
                 fb = (flags & 1) != 0;
                 clamped = (flags & 2) != 0;
-                if (fb) {
-                    const Process pp{PBE_LAW_POWER, p.scheme, p.sol_law, p.cs0, p.cs1, p.alpha, p.cfl, p.dt_max,
-                                     p.t_end};
-                    r = rates_plain(pp, q, Cm, tm);
-                } else {
-                    r.G0 = bcast(crec, 1);
-                    r.B = bcast(crec, 2);
-                    r.S = 0.0;
+                r.G0 = bcast(rec, 0); r.B = bcast(rec, 1); r.S = bcast(rec, 2); r.lnS = bcast(rec, 3);
+                r.arrG = bcast(rec, 4); r.arrB = bcast(rec, 5); r.Sg = bcast(rec, 6); r.Sb = bcast(rec, 7);
+                if (!fb) {
 #pragma unroll
                     for (int i = 0; i < 3; ++i) cz[i] = bcast(crec, 3 + i);
 #pragma unroll
@@ -374,7 +380,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             }
             double dt, ghost, c;
             bool hit;
-            if constexpr (CL == kClosureNone) {
+            if constexpr (REC) {
                 dt = bcast(rec, 8);
                 hit = bcast(rec, 9) != 0.0;
                 ghost = bcast(rec, 10);
@@ -462,7 +468,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             // temperature of the ramp at t^{m-1}, the solubility and its slope,
             // dS/dT = -(C/Csat) Csat'(T) / Csat (plain laws: from the record)
             double Csat, dTdt, dSdT, iT2;
-            if constexpr (CL == kClosureNone) {
+            if constexpr (REC) {
                 Csat = bcast(rec, 12);
                 dSdT = bcast(rec, 13);
                 dTdt = bcast(rec, 14);

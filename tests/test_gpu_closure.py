@@ -105,6 +105,18 @@ def test_fallback_is_the_plain_power_law_bitwise(torch_cuda):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("prec", [W.MLP_FP64, W.MLP_BF16])
+def test_taping_forward_is_the_plain_forward_bitwise(torch_cuda, prec):
+    """A solve that will be differentiated also evaluates the network's input Jacobian (in
+    the spare columns of the same products, or extra sums in fp64) and tapes it: its states,
+    samples and step counts equal those of a solve without checkpoints bit for bit."""
+    prob = closure_problem([64, 129, 300, 700, 1000], prec=prec)
+    a = gpu_solve(prob)
+    b = gpu_solve(prob, ckpt_every=16)
+    for k in ("f", "mom", "C", "steps", "status"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def directions(n, seed):
     rng = np.random.default_rng(seed)
     return [rng.normal(size=W.MLP_NW) for _ in range(n)]
