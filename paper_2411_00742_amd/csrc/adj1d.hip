@@ -217,6 +217,18 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     // plain laws and the learned closure: the recompute pass tapes a record of
     // the step's scalars for the reverse step (the polynomial law forms them again)
     constexpr bool REC = CL == kClosureNone || is_net(CL);
+    // learned closure: the network's input and output scales, loaded once (a
+    // load inside the step would wait, through the in-order memory counter,
+    // for the record prefetches issued before it)
+    double cs_out0 = 0.0, cs_out1 = 0.0, cs_in0 = 0.0, cs_in1 = 0.0, cs_in2 = 0.0;
+    if constexpr (is_net(CL)) {
+        const double* kc = a.cd.c;
+        cs_out0 = uniform(kc[kCOutScale]);
+        cs_out1 = uniform(kc[kCOutScale + 1]);
+        cs_in0 = uniform(kc[kCInScale]);
+        cs_in1 = uniform(kc[kCInScale + 1]);
+        cs_in2 = uniform(kc[kCInScale + 2]);
+    }
     for (int seg = n_seg - 1; seg >= 0; --seg) {
         const int m0 = seg * Kc;
         const int m1 = min(m0 + Kc, n_total);
@@ -487,13 +499,12 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 // closure: ln G0 = a0 + s0 y0 (held at its bound when clamped),
                 // ln B = a1 + s1 y1 with y = net(z), z0 = (S - h0) k0,
                 // z1 = (T - h1) k1, z2 = (log10 mu2 - h2) k2
-                const double* kc = a.cd.c;
-                const double yb0 = clamped ? 0.0 : G0b * r.G0 * uniform(kc[kCOutScale]);
-                const double yb1 = Bb * r.B * uniform(kc[kCOutScale + 1]);
-                const double Sbar = (yb0 * cj[0] + yb1 * cj[1]) * uniform(kc[kCInScale]);
+                const double yb0 = clamped ? 0.0 : G0b * r.G0 * cs_out0;
+                const double yb1 = Bb * r.B * cs_out1;
+                const double Sbar = (yb0 * cj[0] + yb1 * cj[1]) * cs_in0;
                 lamC += Sbar / Csat;
-                Tb = (yb0 * cj[2] + yb1 * cj[3]) * uniform(kc[kCInScale + 1]) + Sbar * dSdT;
-                const double mbar = (yb0 * cj[4] + yb1 * cj[5]) * uniform(kc[kCInScale + 2]) / (cmu2 * 2.302585092994046);
+                Tb = (yb0 * cj[2] + yb1 * cj[3]) * cs_in1 + Sbar * dSdT;
+                const double mbar = (yb0 * cj[4] + yb1 * cj[5]) * cs_in2 / (cmu2 * 2.302585092994046);
                 LaneGeom g6 = g;
                 asm volatile("" : "+v"(g6.xb));
 #pragma unroll
