@@ -182,14 +182,24 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     // t_lo is the last of them, t_lo2 the one before, t_hi the next): carried
     // across steps and loaded one sample ahead of their use, so no step waits
     // on a memory round trip for them
-    int qstep = -1;
-    double q_gc = 0.0, q_gm[4] = {0.0, 0.0, 0.0, 0.0};
+    // (up to 8 cells per lane they stay as loaded until the step that consumes
+    // them, lane j < 4 holding the cotangent of mu_j and lane 4 that of C, so no
+    // step waits on them; the 9-16 class has no registers to spare for that)
+    constexpr bool AHEAD = K <= 8;
+    int qstep_v = -1;
+    double q_v = 0.0, q_gc = 0.0, q_gm[4] = {0.0, 0.0, 0.0, 0.0};
     auto load_sample = [&](int qq) {
         const int64_t o = (int64_t)s * ns + qq;
-        qstep = uniform(a.samp_step[o]);
-        q_gc = A.gC ? uniform(A.gC[o]) : 0.0;
+        if constexpr (AHEAD) {
+            qstep_v = a.samp_step[o];
+            const int j = min(lane, 4);
+            q_v = j < 4 ? (A.gmom ? A.gmom[o * 4 + j] : 0.0) : (A.gC ? A.gC[o] : 0.0);
+        } else {
+            qstep_v = uniform(a.samp_step[o]);
+            q_gc = A.gC ? uniform(A.gC[o]) : 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) q_gm[j] = A.gmom ? uniform(A.gmom[o * 4 + j]) : 0.0;
+            for (int j = 0; j < 4; ++j) q_gm[j] = A.gmom ? uniform(A.gmom[o * 4 + j]) : 0.0;
+        }
     };
     if (qs >= 0) load_sample(qs);
     int nx = ns;
@@ -214,9 +224,8 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     for (int m = 0; m < n_terms; ++m) ga[m * 64 + lane] = 0.0;
 
     const int n_seg = (n_total + Kc - 1) / Kc;
-    // plain laws and the learned closure: the recompute pass tapes a record of
-    // the step's scalars for the reverse step (the polynomial law forms them again)
-    constexpr bool REC = CL == kClosureNone || is_net(CL);
+    // the recompute pass tapes a record of the step's scalars for the reverse step
+    constexpr bool REC = CL == kClosureNone || CL == kClosurePoly || is_net(CL);
     // learned closure: the network's input and output scales, loaded once (a
     // load inside the step would wait, through the in-order memory counter,
     // for the record prefetches issued before it)
@@ -239,6 +248,10 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         double t = uniform(a.ck_t[(int64_t)s * a.n_ckpt + seg]);
         int next = samples_reached(ts, ns, t);
         double t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
+        // up to 8 cells per lane: the sample time after t_next, loaded ahead and
+        // kept as loaded until a step lands on t_next (a load there would wait
+        // behind the tape stores)
+        double t_nn = AHEAD && next + 1 < ns ? ts[next + 1] : p.t_end;
         LaneGeom gm = g;
         asm volatile("" : "+v"(gm.xb));
         double mu3_old = wave_sum(lane_moment3(u, gm)) * dL4;
@@ -250,10 +263,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 tapeT[m - m0] = t;
             }
             Rates r;
+            [[maybe_unused]] PolyTerms ptr{0.0, 0.0, 0.0};
             if constexpr (CL == kClosureNone) {
                 r = rates_plain(p, q, C, t);
             } else if constexpr (CL == kClosurePoly) {
-                r = rates_poly<false>(p, q, C, t, coef, a.n_poly, nullptr);
+                r = rates_poly<true>(p, q, C, t, coef, a.n_poly, &ptr);
             } else {
                 // learned closure: the rates the forward took at this step (the
                 // plain power law where the network's box excluded the state)
@@ -280,9 +294,13 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 const double Csat = solubility(p, Tm);
                 const double dCsat = p.sol_law == PBE_SOL_EXP ? p.cs1 * Csat : p.cs1;
                 const double iT = 1.0 / (Tm + 273.15);
-                const double v[kStepTape] = {r.G0, r.B, r.S, r.lnS, r.arrG, r.arrB, r.Sg, r.Sb, dt, hit ? 1.0 : 0.0,
-                                             ghost, cf, Csat, -(C / Csat) * dCsat / Csat,
-                                             (q.tr > 0.0 && t < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0, iT * iT};
+                // (polynomial law: dG0/dS in place of the Arrhenius growth
+                // factor and S^64 in place of 1/(T + 273.15)^2, which it has no use for)
+                const bool PL = CL == kClosurePoly;
+                const double v[kStepTape] = {r.G0, r.B, r.S, r.lnS, PL ? ptr.dGdS : r.arrG, r.arrB, r.Sg, r.Sb, dt,
+                                             hit ? 1.0 : 0.0, ghost, cf, Csat, -(C / Csat) * dCsat / Csat,
+                                             (q.tr > 0.0 && t < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0,
+                                             PL ? ptr.S64 : iT * iT};
                 if (lane == 0) {
                     double* ts_ = tapeS + (int64_t)(m - m0) * kStepTape;
 #pragma unroll
@@ -296,7 +314,19 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             C = uniform(C - p.alpha * (mu3 - mu3_old));
             mu3_old = mu3;
             t = uniform(hit ? t_next : t + dt);
-            if (hit) {
+            if constexpr (AHEAD) {
+                if (hit && next < ns) {
+                    // landed on sample time ts[next] = t; later samples at the same time are skipped too
+                    ++next;
+                    double tn = uniform(t_nn);
+                    while (next < ns && tn <= t) {
+                        ++next;
+                        tn = uniform(next < ns ? ts[next] : p.t_end);
+                    }
+                    t_next = next < ns ? tn : p.t_end;
+                    t_nn = next + 1 < ns ? ts[next + 1] : p.t_end;
+                }
+            } else if (hit) {
                 while (next < ns && uniform(ts[next]) <= t) ++next;
                 t_next = uniform(next < ns ? ts[min(next, ns - 1)] : p.t_end);
             }
@@ -333,9 +363,10 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 }
             }
             // cotangents of the samples taken at state m
-            while (qs >= 0 && qstep == m) {
-                lamC += q_gc;
-                const double gm4[4] = {q_gm[0], q_gm[1], q_gm[2], q_gm[3]};
+            while (qs >= 0 && uniform(qstep_v) == m) {
+                lamC += AHEAD ? bcast(q_v, 4) : q_gc;
+                const double gm4[4] = {AHEAD ? bcast(q_v, 0) : q_gm[0], AHEAD ? bcast(q_v, 1) : q_gm[1],
+                                       AHEAD ? bcast(q_v, 2) : q_gm[2], AHEAD ? bcast(q_v, 3) : q_gm[3]};
                 LaneGeom g3 = g;
                 asm volatile("" : "+v"(g3.xb));
                 double gcell[K];
@@ -353,7 +384,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 }
                 --qs;
                 if (qs >= 0) load_sample(qs);
-                else qstep = -1;
+                else qstep_v = -1;
             }
 
             // samples reached at tm (the forward's sample index at step m-1)
@@ -374,7 +405,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
                 r.G0 = bcast(rec, 0); r.B = bcast(rec, 1); r.S = bcast(rec, 2); r.lnS = bcast(rec, 3);
                 r.arrG = bcast(rec, 4); r.arrB = bcast(rec, 5); r.Sg = bcast(rec, 6); r.Sb = bcast(rec, 7);
             } else if constexpr (CL == kClosurePoly) {
-                r = rates_poly<true>(p, q, Cm, tm, coef, a.n_poly, &pt);
+                r.G0 = bcast(rec, 0); r.B = bcast(rec, 1); r.S = bcast(rec, 2); r.lnS = bcast(rec, 3);
+                r.arrG = 1.0; r.arrB = bcast(rec, 5); r.Sg = bcast(rec, 6); r.Sb = bcast(rec, 7);
+                pt.dGdS = bcast(rec, 4);
+                pt.S64 = bcast(rec, 15);
+                pt.Sl = r.S > 0.0 ? exp64((double)(lane + 1) * r.lnS) : 0.0;
             } else {
                 // the rates from the record (the power law's where the network fell back)
                 const int flags = (int)bcast(crec, 0);
