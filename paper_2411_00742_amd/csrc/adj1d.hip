@@ -257,11 +257,6 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         double mu3_old = wave_sum(lane_moment3(u, gm)) * dL4;
         double crn = is_net(CL) ? tapeR[(int64_t)m0 * kClosureTape + rj] : 0.0;   // one step ahead
         for (int m = m0; m < m1; ++m) {
-            store_cells(u, tape + (int64_t)(m - m0) * N, i0, g.npad);
-            if (lane == 0) {
-                tapeC[m - m0] = C;
-                tapeT[m - m0] = t;
-            }
             Rates r;
             [[maybe_unused]] PolyTerms ptr{0.0, 0.0, 0.0};
             if constexpr (CL == kClosureNone) {
@@ -306,6 +301,13 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
 #pragma unroll
                     for (int j = 0; j < kStepTape; ++j) ts_[j] = v[j];
                 }
+            }
+            // the state the step starts from, taped after the rates so that their
+            // loads do not wait for these stores
+            store_cells(u, tape + (int64_t)(m - m0) * N, i0, g.npad);
+            if (lane == 0) {
+                tapeC[m - m0] = C;
+                tapeT[m - m0] = t;
             }
             (void)fvm_step<K, PBE_SCHEME_SSPRK3>(u, g, cf, ghost);
             LaneGeom g2 = g;
