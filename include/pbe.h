@@ -295,9 +295,11 @@ typedef struct {
 } pbe_tuning;
 
 /* Autotuner: time candidate launch shapes on this handle's own problem and
- * keep the fastest (2D: column-block length 64, 128, 256 or 512 rows).  Each
- * candidate runs the solve from the initial condition, limited to trial_steps
- * steps per simulation (0: to t_end), timed with HIP events.  2D results agree
+ * keep the fastest (2D: column-block length 32, 64, 128 or 256 rows; a
+ * candidate replaces the default of 64 only when its trial is at least 3%
+ * faster, smaller differences being timing noise).  Each candidate runs the
+ * solve from the initial condition, limited to trial_steps steps per
+ * simulation (0: to t_end), timed with HIP events from the first step on.  2D results agree
  * to rounding (the moment partial sums are grouped by column block).  The
  * choice is cached per process under the problem's shape (dimension, sizes,
  * closure variant); with use_cache != 0 a cached choice is applied without
