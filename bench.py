@@ -241,7 +241,7 @@ def fvm2d_leg(steps: int, splitting: int = 0):
     from paper_2411_00742_amd import workloads as W
     prob = W.shape_2d().with_(splitting=splitting)
     solver = pbe.Solver(prob)
-    tuning = solver.tune(trial_steps=30)   # tile height chosen by the autotuner (pbe_tune)
+    tuning = solver.tune(trial_steps=60)   # tile height chosen by the autotuner (pbe_tune)
     out = solver.solve()
     torch.cuda.synchronize()
     st = out["steps"].cpu().numpy().astype(np.int64)

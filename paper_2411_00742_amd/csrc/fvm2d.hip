@@ -129,17 +129,12 @@ __device__ void finalize_sim(const Fvm2dArgs& a, int s, int init) {
     double C, t, out, mu0 = 0.0;
     int step, next, status;
     if (init) {
-        // volume moment of the initial state (midpoint rule, SI Eq. (S5))
-        const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
+        // volume moment of the initial state (midpoint rule, SI Eq. (S5)):
+        // the tile partials k_init2d left, summed in tile order
         double m12 = 0.0;
-        for (int j = 0; j < n2; ++j) {
-            const double L2c = (j + 0.5) * d2;
-            for (int i = lane; i < n1; i += 64) {
-                const double L1c = (i + 0.5) * d1;
-                m12 = fma(L1c * L2c * L2c, a.f0[o + (int64_t)j * n1 + i], m12);
-            }
-        }
-        m12 = wave_sum(m12) * d1 * d2;
+        const int b0 = uniform(a.cb_first[s]), b1 = uniform(a.cb_first[s + 1]);
+        for (int bb = b0 + lane; bb < b1; bb += 64) m12 += a.part[(int64_t)bb * 5 + 3];
+        m12 = wave_sum(m12);
         C = uniform(a.C0[s]);
         t = 0.0;
         out = 0.0;
@@ -374,6 +369,32 @@ __global__ __launch_bounds__(64) void k_step2d(Fvm2dArgs a, int parity) {
     }
 }
 
+// Volume moment mu_{1,2} of the initial state, one partial per tile (the
+// tiles of the step kernel: its owned columns x its rows), so that the start
+// of a solve reads each simulation once across the whole chip instead of
+// with one wavefront per simulation.
+__global__ __launch_bounds__(64) void k_init2d(Fvm2dArgs a, int tile_width) {
+    const int b = tile_of_block((int)blockIdx.x, (int)gridDim.x);
+    if (b >= a.n_cb) return;
+    const int s = uniform(a.cb_sim[b]);
+    const int lane = threadIdx.x;
+    const int n1 = uniform(a.n1[s]), n2 = uniform(a.n2[s]);
+    const int c0 = uniform(a.cb_col0[b]), r0 = uniform(a.cb_row0[b]);
+    const int r1 = min(r0 + a.seg, n2);
+    const int col = c0 + lane;
+    const bool own = lane < tile_width && col < n1;
+    const int64_t o = (int64_t)uniform((int)a.off[s]) | ((int64_t)uniform((int)(a.off[s] >> 32)) << 32);
+    const double d1 = uniform(a.L1[s]) / n1, d2 = uniform(a.L2[s]) / n2;
+    const double* src = a.f0 + o + min(col, n1 - 1);
+    double m = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        const double L2c = (r + 0.5) * d2;
+        m = fma(L2c * L2c, src[(int64_t)r * n1], m);
+    }
+    const double m12 = wave_sum(own ? (col + 0.5) * d1 * m : 0.0) * d1 * d2;
+    if (lane == 0) a.part[(int64_t)b * 5 + 3] = m12;
+}
+
 // final state of every sim (it sits in buf[steps % 2]) into a packed output
 __global__ void k_out2d(Fvm2dArgs a, double* f_out) {
     const int s = blockIdx.y;
@@ -407,6 +428,12 @@ hipError_t launch_step2d(const Fvm2dArgs& a, int parity, hipStream_t st) {
 }
 
 hipError_t launch_final2d(const Fvm2dArgs& a, int init, hipStream_t st) {
+    if (init) {   // the initial volume moment's tile partials first
+        const int blocks = (a.n_cb + 7) / 8 * 8;
+        hipLaunchKernelGGL(k_init2d, dim3(blocks), dim3(64), 0, st, a, step2d_tile_width(a.scheme, a.strang));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_final2d, dim3(a.n_sims), dim3(64), 0, st, a, init);
     return hipGetLastError();
 }

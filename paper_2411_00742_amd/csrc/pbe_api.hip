@@ -769,12 +769,22 @@ int tune_handle(pbe_handle* h, int trial_steps, bool use_cache, pbe_tuning* out)
     }
     int best = -1;
     float best_ms = 0.0f, default_ms = 0.0f;
+    {
+        // the device's clocks settle before the first candidate is timed: the
+        // default goes first and would otherwise be timed on a cold device
+        int rc = apply_tuning(h, cands[0]);
+        float ms = 0.0f;
+        for (int w = 0; w < 3 && rc == PBE_OK; ++w) rc = trial_ms(h, trial_steps, &ms);
+        if (rc != PBE_OK) return rc;
+    }
     for (size_t i = 0; i < cands.size(); ++i) {
         int rc = apply_tuning(h, cands[i]);
-        float ms = 0.0f;
+        float ms = 0.0f, ms2 = 0.0f;
         if (rc == PBE_OK) rc = trial_ms(h, trial_steps, &ms);   // warm-up
         if (rc == PBE_OK) rc = trial_ms(h, trial_steps, &ms);
+        if (rc == PBE_OK) rc = trial_ms(h, trial_steps, &ms2);  // the faster of two timed trials
         if (rc != PBE_OK) return rc;
+        ms = std::min(ms, ms2);
         if (i == 0) default_ms = ms;
         if (best < 0 || ms < best_ms) {
             best = (int)i;
