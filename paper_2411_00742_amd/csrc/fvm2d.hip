@@ -28,6 +28,8 @@
 //             into the tile kernel with a last-tile ticket needs a device-scope
 //             release per tile, which writes back the L2 of the tile's XCD:
 //             three times slower in total.)
+// At the start of a solve, k_init2d sums the initial state's volume moment
+// per tile and k_final2d (init) adds those partials and prepares step 0.
 #include <type_traits>
 
 #include "fvm1d_device.h"
