@@ -15,6 +15,10 @@ namespace {
 
 using namespace dev;
 
+// polynomial law: the running simulation's coefficients (one array for every
+// instantiation of run_sim, so a kernel holds 8 KB of LDS, not 8 KB per lane count)
+__shared__ double poly_lds[kMaxPoly];
+
 // W = 1: one wavefront per simulation; W = 2: a wave pair (see Pair), with
 // `lane` the global lane 0..127 of the right-aligned layout.
 template <int K, int SCHEME, int CL, int W>
@@ -47,6 +51,17 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         if (lane < PBE_CORR_NW) wsh[lane] = a.corr[(int64_t)s * PBE_CORR_NW + lane];
         __syncthreads();
         corr_w = wsh;
+    }
+
+    // polynomial law: the sim's coefficients, staged in LDS once per simulation
+    // (read every step; a global load there would wait, through the in-order
+    // memory counter, for the sample stores of the step before)
+    [[maybe_unused]] const double* coef = nullptr;
+    if constexpr (CL == kClosurePoly) {
+        __syncthreads();   // the previous simulation's reads are done
+        for (int j = lane; j < a.n_poly; j += 64) poly_lds[j] = a.poly[(int64_t)s * a.n_poly + j];
+        __syncthreads();
+        coef = poly_lds;
     }
 
     double u[K];
@@ -85,7 +100,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         } else if constexpr (CL == kCorrect) {
             r = rates_plain(p, q, C, t);
         } else if constexpr (CL == kClosurePoly) {
-            r = rates_poly<false>(p, q, C, t, a.poly + (int64_t)s * a.n_poly, a.n_poly, nullptr);
+            r = rates_poly<false>(p, q, C, t, coef, a.n_poly, nullptr);
         } else {
             // learned closure: inputs S, T and mu_2 of the current state
             LaneGeom g2 = g;
