@@ -87,6 +87,34 @@ def test_adjoint_matches_oracle_tangent(torch_cuda, oracle, record_f):
         assert_close(g[s], ref, s)
 
 
+def test_adjoint_is_deterministic_and_independent_of_the_batch(torch_cuda):
+    """Each simulation's reverse walk runs on its own wavefront with its own tapes: the gradient
+    of a simulation is bitwise the same when it runs alone as in a batch (its tape, step record
+    and sample cotangents are not mixed with its neighbours'), and a second pbe_grad of the same
+    solve repeats the first bit for bit.  Sample-dense (a sample every few steps) and sparse
+    sims, both adjoint classes."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    sizes = [64, 200, 300, 511, 700, 1000]
+    prob = small_estimation(len(sizes), sizes, t_end=300.0)
+    prob = prob.with_(t_samples=np.linspace(5.0, 300.0, 60))
+    s = pbe.Solver(prob, ckpt_every=16, record_f=True)
+    o = {k: v.cpu().numpy() for k, v in s.solve().items()}
+    gf, gmom, gC = scale_cotangents(prob, o, *cotangents(prob, True, 5))
+    gf, gmom, gC = torch.tensor(gf), torch.tensor(gmom), torch.tensor(gC)
+    g1 = s.grad(gf, gmom, gC).cpu().numpy()
+    g2 = s.grad(gf, gmom, gC).cpu().numpy()
+    s.close()
+    np.testing.assert_array_equal(g1, g2)
+    off, ns = prob.offsets(), len(prob.t_samples)
+    for k in (0, 3, 5):
+        one = pbe.Solver(prob.subset([k]), ckpt_every=16, record_f=True)
+        one.solve()
+        gk = one.grad(gf[off[k] * ns:off[k + 1] * ns].clone(), gmom[k:k + 1].clone(), gC[k:k + 1].clone())
+        one.close()
+        np.testing.assert_array_equal(gk.cpu().numpy()[0], g1[k])
+
+
 def test_adjoint_matches_central_differences_of_gpu_forward(torch_cuda):
     """Loss = sum of squared relative moment/C errors against fixed targets; central differences
     of the GPU forward (the step schedule is dt_max-limited here, so it does not move)."""
