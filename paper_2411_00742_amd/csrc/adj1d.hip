@@ -600,13 +600,17 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
 }
 
 // Adjoint classes: cells per lane 1-8 and 9-16 (grids up to 1024 cells).
-// waves per SIMD each adjoint class is held to: two for the 1-8 class (what it
-// spills lies outside the step loops; a second wave per SIMD hides more
-// latency), one for the 9-16 class
-constexpr int adj_waves_per_simd(int klo) { return klo == 1 ? 2 : 1; }
+// waves per SIMD each adjoint class is held to: two for the 1-8 class of the
+// plain and polynomial laws (what it spills lies outside the step loops; a
+// second wave per SIMD hides more latency), one for the 9-16 class and for the
+// learned closure, whose 1-8 class at two waves spills the step record's
+// prefetch inside the reverse loop (each spill waits for the loads before it)
+constexpr int adj_waves_per_simd(int klo, int cl) {
+    return klo == 1 && cl != kClosureBf16 && cl != kClosureFp64 ? 2 : 1;
+}
 
 template <int KLO, int CL>
-__global__ __launch_bounds__(64, adj_waves_per_simd(KLO)) void k_adj1d(Adj1dArgs A, int cls_begin, int cls_count, int32_t* queue) {
+__global__ __launch_bounds__(64, adj_waves_per_simd(KLO, CL)) void k_adj1d(Adj1dArgs A, int cls_begin, int cls_count, int32_t* queue) {
     // the three SSP-RK3 stage input states of the step being reversed and the
     // direct part of its adjoint (each lane owns its column)
     __shared__ double lds[4 * (KLO + 7) * 64 + (CL == kClosurePoly ? kMaxPoly : 0)];
