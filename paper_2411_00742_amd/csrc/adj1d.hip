@@ -15,11 +15,15 @@
 // One wavefront per simulation, same register layout as the forward kernel.
 // For each checkpoint segment (ckpt_every steps), last to first:
 //   1. reload the checkpoint (f, C, t) and recompute the segment forward with
-//      the forward kernel's step, writing the state at each step to a tape;
+//      the forward kernel's step, writing the state at each step to a tape and
+//      the step's scalars (rates, step size, ghost, Courant factor, solubility
+//      terms) to a per-step record (the learned closure's rates come from the
+//      record its forward solve kept of every step);
 //   2. walk the segment backwards: for step m-1 -> m, recompute the three
 //      SSP-RK3 stage states on-chip from the taped f^{m-1}, then apply the
 //      transposed Jacobians of the stages, the solute balance (Eq. (9)) and
-//      the rate laws, adding sample cotangents as their steps are reached.
+//      the rate laws (their values read from the record, one step ahead),
+//      adding sample cotangents as their steps are reached.
 // Derivative conventions: the limited slope psi = 2ab/(a+b) for ab > 0 has
 // zero derivative where ab <= 0; max(S, 0) and S^p have zero derivative at S <= 0.
 #include "closure_device.h"
