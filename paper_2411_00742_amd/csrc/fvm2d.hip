@@ -107,7 +107,7 @@ __device__ __forceinline__ double col_feed(ColStage& st, double x, double c, dou
     return out;
 }
 
-constexpr int kColAhead = 12;   // row loads in flight per wave
+constexpr int kColAhead = 8;   // row loads in flight per wave
 
 // Block b -> tile: the hardware hands consecutive blocks to the 8 XCDs in
 // turn, so blocks b, b + 8, b + 16, ... share an XCD (and its L2).  They get
@@ -226,8 +226,10 @@ struct Tile2d {
     static constexpr int width = STRANG ? 64 - 2 * (H::left + H::right) : H::width;
 };
 
+// (held to four waves per SIMD: left to itself the compiler gives the SSP-RK3
+// tile 140 registers, three waves per SIMD)
 template <int SCHEME, bool STRANG>
-__global__ __launch_bounds__(64) void k_step2d(Fvm2dArgs a, int parity) {
+__global__ __launch_bounds__(64, 4) void k_step2d(Fvm2dArgs a, int parity) {
     using H = Halo2d<SCHEME>;
     using TL = Tile2d<SCHEME, STRANG>;
     constexpr bool RK = SCHEME == PBE_SCHEME_SSPRK3;
