@@ -203,7 +203,9 @@ def closure_leg(steps: int):
         plain_s += time.perf_counter() - t1
         plain_cells += int(o1["steps"].cpu()[0]) * int(prob.n_cells[sidx])
         one.close()
-    tr = pbe.Solver(prob, ckpt_every=32)
+    # checkpointed at every step: the forward keeps every state (62 GB here), the adjoint
+    # recomputes nothing
+    tr = pbe.Solver(prob, ckpt_every=1)
     w = torch.tensor(prob.mlp[:W.MLP_NW], device="cuda")
     opt = pbe.Adam(w, lr=1e-3)
     o = tr.solve()

@@ -173,7 +173,10 @@ int pbe_reset(pbe_handle *h);
  * With ckpt_every > 0 the forward pass also stores checkpoints for pbe_grad;
  * under law == MLP it also evaluates the network's input Jacobian at every step
  * and keeps it with the step's network inputs and rates (104 B per sim-step,
- * sized by the step cap), so that pbe_grad does not evaluate the network again. */
+ * sized by the step cap), so that pbe_grad does not evaluate the network again;
+ * with ckpt_every == 1 it keeps every step's state and step scalars (8 B per
+ * cell and 128 B per sim per step, sized by the step cap) and pbe_grad
+ * recomputes nothing. */
 int pbe_solve(pbe_handle *h, double *f_out, double *mom_out, double *C_out,
               int32_t *steps_out, int32_t *status_out);
 

@@ -227,7 +227,11 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
     const int n_terms = CL == kClosurePoly ? (a.n_poly + 63) >> 6 : 0;
     for (int m = 0; m < n_terms; ++m) ga[m * 64 + lane] = 0.0;
 
-    const int n_seg = (n_total + Kc - 1) / Kc;
+    // learned closure checkpointed at every step: the forward kept every state
+    // and every step's scalars, so the whole trajectory is one segment with
+    // nothing to recompute
+    const bool every = is_net(CL) && a.ck_s != nullptr && Kc == 1;
+    const int n_seg = every ? 1 : (n_total + Kc - 1) / Kc;
     // the recompute pass tapes a record of the step's scalars for the reverse step
     constexpr bool REC = CL == kClosureNone || CL == kClosurePoly || is_net(CL);
     // learned closure: the network's input and output scales, loaded once (a
@@ -243,8 +247,12 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         cs_in2 = uniform(kc[kCInScale + 2]);
     }
     for (int seg = n_seg - 1; seg >= 0; --seg) {
-        const int m0 = seg * Kc;
-        const int m1 = min(m0 + Kc, n_total);
+        const int m0 = every ? 0 : seg * Kc;
+        const int m1 = every ? n_total : min(m0 + Kc, n_total);
+        // the segment's states and step records: the forward's own with `every`
+        const double* tp = every ? a.ck_f + base * a.n_ckpt : tape;
+        const double* tsp = every ? a.ck_s + (int64_t)s * a.step_cap * kStepTape : tapeS;
+        if (!every) {
         // ---- recompute the segment forward, taping the state at each step
         double u[K];
         load_cells(u, a.ck_f + base * a.n_ckpt + (int64_t)seg * N, i0, g.npad, 0.0);
@@ -338,6 +346,7 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
             }
         }
         // (each lane reads back only the tape addresses it wrote itself)
+        }
 
         // ---- reverse walk over the segment
         // taped scalars of the first reverse step; each step prefetches the
@@ -348,20 +357,20 @@ __device__ __forceinline__ void adjoint_sim(const Adj1dArgs& A, int s, double* _
         // cover the state load above it) and needs neither C nor t.
         double Cn = REC ? 0.0 : uniform(tapeC[m1 - 1 - m0]);
         double tn = REC ? 0.0 : uniform(tapeT[m1 - 1 - m0]);
-        double recn = REC ? tapeS[(int64_t)(m1 - 1 - m0) * kStepTape + (lane & (kStepTape - 1))] : 0.0;
+        double recn = REC ? tsp[(int64_t)(m1 - 1 - m0) * kStepTape + (lane & (kStepTape - 1))] : 0.0;
         // learned closure: the step's taped closure quantities, also one step ahead
         double crecn = is_net(CL) ? tapeR[(int64_t)(m1 - 1) * kClosureTape + rj] : 0.0;
         for (int m = m1; m > m0; --m) {
             // state at m-1 from the tape: issued first, consumed after the rates
             double u0[K];
-            load_cells(u0, tape + (int64_t)(m - 1 - m0) * N, i0, g.npad, 0.0);
+            load_cells(u0, tp + (int64_t)(m - 1 - m0) * N, i0, g.npad, 0.0);
             const double Cm = Cn;
             const double tm = tn;
             const double rec = recn;
             const double crec = crecn;
             if (m - 1 > m0) {
                 if constexpr (REC) {
-                    recn = tapeS[(int64_t)(m - 2 - m0) * kStepTape + (lane & (kStepTape - 1))];
+                    recn = tsp[(int64_t)(m - 2 - m0) * kStepTape + (lane & (kStepTape - 1))];
                     if constexpr (is_net(CL)) crecn = tapeR[(int64_t)(m - 2) * kClosureTape + rj];
                 } else {
                     Cn = uniform(tapeC[m - 2 - m0]);

@@ -21,7 +21,10 @@ __shared__ double poly_lds[kMaxPoly];
 
 // W = 1: one wavefront per simulation; W = 2: a wave pair (see Pair), with
 // `lane` the global lane 0..127 of the right-aligned layout.
-template <int K, int SCHEME, int CL, int W>
+// TAPE (learned closure, a solve that will be differentiated): also evaluate the
+// network's input Jacobian and tape the step for the adjoint; its own kernel
+// instantiation, so that the solves without it keep their registers.
+template <int K, int SCHEME, int CL, int W, bool TAPE = false>
 __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
     static_assert(W == 1 || CL == kClosureNone, "the closure and dissolution kernels run one wavefront per simulation");
     const int lane = W == 2 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
@@ -93,6 +96,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         asm volatile("" : "+v"(g.xb));
         if (step >= a.step_cap) { status |= PBE_SIM_STEPCAP; break; }
         Rates r;
+        [[maybe_unused]] bool net_fallback = false;
         if constexpr (CL == kClosureNone) {
             r = rates_plain(p, q, C, t);
         } else if constexpr (CL == kDissolve) {
@@ -107,7 +111,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             asm volatile("" : "+v"(g2.xb));
             const double mu2 = wave_sum(lane_moment2(u, g2)) * dL3;
             ClosureRates cr;
-            if (a.ck_r) {
+            if constexpr (TAPE) {
                 // a solve that will be differentiated: also the network's input
                 // Jacobian (the tangent columns of the same matrix products),
                 // taped with the step's inputs and rates for the adjoint
@@ -130,6 +134,7 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
             r.G0 = cr.G0;
             r.B = cr.B;
             r.S = cr.S;
+            net_fallback = cr.fallback;
             if (cr.fallback) status |= PBE_SIM_FALLBACK;
         }
         double dt;
@@ -158,6 +163,35 @@ __device__ __forceinline__ void run_sim(const Fvm1dArgs& a, int s, Pair* pr) {
         }
 
         const double cour = courant(dt, r.G0, inv_dL);
+        if constexpr (TAPE) {
+            if (a.ck_s) {
+                // checkpointed at every step: also the scalars the adjoint's
+                // reverse step reads (the rates of the plain power law where the
+                // network fell back, the step size, ghost, Courant factor and
+                // solubility terms), formed as the adjoint's recompute would
+                Rates rr;
+                if (net_fallback) {
+                    const Process pp{PBE_LAW_POWER, p.scheme, p.sol_law, p.cs0, p.cs1, p.alpha, p.cfl, p.dt_max,
+                                     p.t_end};
+                    rr = rates_plain(pp, q, C, t);
+                } else {
+                    rr.G0 = r.G0; rr.B = r.B;
+                    rr.S = 0.0; rr.lnS = 0.0; rr.arrG = 1.0; rr.arrB = 1.0; rr.Sg = 0.0; rr.Sb = 0.0;
+                }
+                const double Tm = temperature(q, t);
+                const double Csat = solubility(p, Tm);
+                const double dCsat = p.sol_law == PBE_SOL_EXP ? p.cs1 * Csat : p.cs1;
+                const double iT = 1.0 / (Tm + 273.15);
+                const double v[kStepTape] = {rr.G0, rr.B, rr.S, rr.lnS, rr.arrG, rr.arrB, rr.Sg, rr.Sb, dt,
+                                             hit ? 1.0 : 0.0, ghost, cour, Csat, -(C / Csat) * dCsat / Csat,
+                                             (q.tr > 0.0 && t < q.tr) ? (q.T1 - q.T0) * q.inv_tr : 0.0, iT * iT};
+                if (lane == 0) {
+                    double* rec = a.ck_s + ((int64_t)s * a.step_cap + step) * kStepTape;
+#pragma unroll
+                    for (int j = 0; j < kStepTape; ++j) rec[j] = v[j];
+                }
+            }
+        }
         double hN;
         if constexpr (CL == kDissolve) {
             if (cour < 0.0) {   // dissolving: nothing crosses L_max
@@ -240,17 +274,17 @@ constexpr int fvm_waves_per_simd(int klo, int cl) {   // (kDissolve: as the plai
 }
 
 // run simulation s with its K (uniform) in [KA, KHI]: a chain of scalar branches
-template <int KA, int KHI, int SCHEME, int CL>
+template <int KA, int KHI, int SCHEME, int CL, bool TAPE = false>
 __device__ __forceinline__ void run_k(const Fvm1dArgs& a, int s, int K) {
     if constexpr (KA <= KHI) {
         if (K == KA)
-            run_sim<KA, SCHEME, CL, 1>(a, s, nullptr);
+            run_sim<KA, SCHEME, CL, 1, TAPE>(a, s, nullptr);
         else
-            run_k<KA + 1, KHI, SCHEME, CL>(a, s, K);
+            run_k<KA + 1, KHI, SCHEME, CL, TAPE>(a, s, K);
     }
 }
 
-template <int SCHEME, int KLO, int KHI, int CL>
+template <int SCHEME, int KLO, int KHI, int CL, bool TAPE = false>
 __global__ __launch_bounds__(64, fvm_waves_per_simd(KLO, CL)) void k_fvm1d(Fvm1dArgs a, int cls_begin, int cls_count,
                                                                         int32_t* queue) {
     // Longer grids get higher issue priority where waves of different classes
@@ -270,7 +304,7 @@ __global__ __launch_bounds__(64, fvm_waves_per_simd(KLO, CL)) void k_fvm1d(Fvm1d
         if (idx >= cls_count) break;
         const int s = uniform(a.order[cls_begin + idx]);
         const int K = uniform((a.ncell[s] + 63) >> 6);
-        run_k<KLO, KHI, SCHEME, CL>(a, s, K);
+        run_k<KLO, KHI, SCHEME, CL, TAPE>(a, s, K);
     }
 }
 
@@ -341,8 +375,24 @@ static hipError_t launch_closure_class(int cls, const Fvm1dArgs& a, int n_blocks
                                        hipStream_t st) {
     constexpr int R = PBE_SCHEME_SSPRK3;
     switch (cls) {
-        case 0: hipLaunchKernelGGL((k_fvm1d<R, 1, 8, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
-        case 1: hipLaunchKernelGGL((k_fvm1d<R, 9, 16, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q); break;
+        case 0:
+            if constexpr (CL == kClosureBf16 || CL == kClosureFp64) {
+                if (a.ck_r) {   // a solve that will be differentiated
+                    hipLaunchKernelGGL((k_fvm1d<R, 1, 8, CL, true>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
+                    break;
+                }
+            }
+            hipLaunchKernelGGL((k_fvm1d<R, 1, 8, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
+            break;
+        case 1:
+            if constexpr (CL == kClosureBf16 || CL == kClosureFp64) {
+                if (a.ck_r) {
+                    hipLaunchKernelGGL((k_fvm1d<R, 9, 16, CL, true>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
+                    break;
+                }
+            }
+            hipLaunchKernelGGL((k_fvm1d<R, 9, 16, CL>), dim3(n_blocks), dim3(64), 0, st, a, begin, count, q);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1005,6 +1005,9 @@ int pbe_create(const pbe_problem* p, void* hip_stream, pbe_handle** out) {
             h->n_partial = 1024;
             // the closure quantities of every step, taped by the forward for the adjoint
             a.ck_r = m.get<double>((size_t)S * step_cap * kClosureTape);
+            // checkpointed at every step: the step scalars too (the adjoint then
+            // recomputes nothing)
+            if (p->ckpt_every == 1) a.ck_s = m.get<double>((size_t)S * step_cap * kStepTape);
             h->d_rows = m.get<double>((size_t)S * h->row_cap * 5);
             h->d_partial = m.get<double>((size_t)h->n_partial * PBE_MLP_NW);
             h->d_gmlp = m.get<double>(PBE_MLP_NW);

@@ -42,6 +42,11 @@ constexpr int kMaxPoly = 1024;   // polynomial coefficients per simulation
 // G0, B, z0, z1, z2, dy0/dz_i and dy1/dz_i for i = 0, 1, 2 (pairs), mu2
 constexpr int kClosureTape = 13;
 
+// per taped step, as the forward formed them: G0, B, S,
+// ln S, the two Arrhenius factors, S^g, S^b, dt, landed-on-a-sample flag,
+// inflow ghost, Courant factor, Csat(T), dS/dT, dT/dt, 1/(T + 273.15)^2
+constexpr int kStepTape = 16;
+
 // Everything the 1D forward kernel reads or writes.  Device pointers only.
 struct Fvm1dArgs {
     int32_t n_sims, n_samples;
@@ -88,6 +93,9 @@ struct Fvm1dArgs {
     // learned closure with checkpoints: [S][step_cap][kClosureTape] the closure
     // quantities of every step, taped by the forward for the adjoint; else null
     double* ck_r;
+    // learned closure checkpointed at every step: [S][step_cap][kStepTape] the
+    // step scalars of every step, so the adjoint recomputes nothing; else null
+    double* ck_s;
 };
 
 // Adjoint of the 1D solve (reverse sweep over checkpointed segments).
@@ -106,10 +114,6 @@ struct Adj1dArgs {
     int32_t gf_is_final;       // 1: gf is the cotangent of the final state (no RECORD_F)
     double* gpoly;             // polynomial law: [S][n_poly] d/d(a_1..a_k) output
 };
-// per taped step of the plain laws, as the forward formed them: G0, B, S,
-// ln S, the two Arrhenius factors, S^g, S^b, dt, landed-on-a-sample flag,
-// inflow ghost, Courant factor, Csat(T), dS/dT, dT/dt, 1/(T + 273.15)^2
-constexpr int kStepTape = 16;
 
 // 2D Godunov-split solver: per global step one pass over tiles that sweeps
 // L1 and then L2 (double buffered) with moment partials, and a per-sim finalize.

@@ -117,6 +117,36 @@ def test_taping_forward_is_the_plain_forward_bitwise(torch_cuda, prec):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("prec", [W.MLP_FP64, W.MLP_BF16])
+def test_checkpoint_every_step_gives_the_same_gradients_bitwise(torch_cuda, prec):
+    """Checkpointed at every step, the forward keeps every state and every step's scalars and
+    the adjoint recomputes nothing; the per-sim and weight gradients equal those of a solve
+    checkpointed every 16 steps (which recomputes them) bit for bit, fallback steps included."""
+    import torch
+    import paper_2411_00742_amd as pbe
+    blob = blob_with_biases()
+    blob[W.MLP_NW + 16] = 0.035     # s_min inside the range the first sim crosses: its early steps fall back
+    prob = closure_problem([100, 257, 640, 1000], t_end=300.0, prec=prec, blob=blob)
+    prob.par[:, W.P_GAMMA] = [0.0, 5e-4, 1.2e-3, 2e-4]
+    res = []
+    for ck in (16, 1):
+        s = pbe.Solver(prob, ckpt_every=ck)
+        o = {k: v.cpu().numpy() for k, v in s.solve().items()}
+        rng = np.random.default_rng(5)
+        gmom = rng.normal(size=o["mom"].shape) / np.abs(o["mom"])
+        gC = rng.normal(size=o["C"].shape) / np.abs(o["C"])
+        gpar, gw = s.grad(None, torch.tensor(gmom), torch.tensor(gC), with_mlp=True)
+        res.append((o, gpar.cpu().numpy(), gw.cpu().numpy()))
+        s.close()
+    (oa, pa, wa), (ob, pb, wb) = res
+    assert np.any(oa["status"] & 4), "no step fell back to the plain law"
+    for k in ("f", "mom", "C", "steps", "status"):
+        np.testing.assert_array_equal(oa[k], ob[k])
+    assert np.all(np.isfinite(pa)) and np.all(np.isfinite(wa))
+    np.testing.assert_array_equal(pa, pb)
+    np.testing.assert_array_equal(wa, wb)
+
+
 def directions(n, seed):
     rng = np.random.default_rng(seed)
     return [rng.normal(size=W.MLP_NW) for _ in range(n)]
